@@ -1,0 +1,192 @@
+"""Seeded synthetic workloads: lattice sizes, parameters and initial fields.
+
+This module holds no arithmetic of the method itself.  It only draws seeded
+geometry (disks, slug bands, inlet-colour schedules) and fixes the parameter
+recipes of the benchmark cases, so that the FP64 oracle and the HIP library
+receive byte-identical inputs.  Relaxation times are derived from viscosity
+ratios with the lattice relation tau = 3 nu + 1/2 of the paper's Sec. 2.1.1;
+densities are sharp phase indicators times the reference densities.
+
+Cases (stand-ins for the paper's own runs, which used data that is not
+available; the paper's sizes and parameters are quoted where they exist):
+
+* ``static_bubble``  -- square periodic lattice, a disk of one fluid in the
+  other (Sec. 4 square-to-droplet / Laplace tests).
+* ``bubble_sweep``   -- 512 x 512 bubbles, density ratio gamma in
+  {10, 100, 1000} x dynamic-viscosity ratio M in {1, 10, 100}.
+* ``gravity_slug``   -- periodic channel with walls, body force, alternating
+  heavy/light slugs (Sec. 5.1 periodic case).
+* ``inlet_outlet``   -- channel with a velocity inlet, pressure outlet and
+  walls; the inlet colour alternates on a seeded schedule (Sec. 5.2).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+DEFAULTS = dict(bc_x="periodic", bc_y="periodic", collision="bgk", storage="f32",
+                rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0, tau_b=1.0,
+                delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8, gx=0.0, gy=0.0,
+                u_in_r=0.0, u_in_b=0.0, p_out=0.0)
+
+
+def params(**kw):
+    """A full parameter dict (the fields of the C struct ``lbm_params``)."""
+    p = dict(DEFAULTS)
+    unknown = set(kw) - set(DEFAULTS) - {"nx", "ny"}
+    if unknown:
+        raise KeyError(f"unknown parameters: {sorted(unknown)}")
+    p.update(kw)
+    return p
+
+
+def tau_from_nu(nu: float) -> float:
+    return 3.0 * nu + 0.5
+
+
+def nu_from_tau(tau: float) -> float:
+    return (tau - 0.5) / 3.0
+
+
+def disk_fields(nx, ny, cx, cy, radius, rho_in, rho_out, inside_red=True):
+    """Sharp disk: node (x, y) is inside iff its cell centre (x+1/2, y+1/2)
+    lies strictly within ``radius`` of (cx, cy)."""
+    y, x = np.mgrid[0:ny, 0:nx]
+    inside = (x + 0.5 - cx) ** 2 + (y + 0.5 - cy) ** 2 < radius ** 2
+    red = inside if inside_red else ~inside
+    rho_r = np.where(red, rho_in if inside_red else rho_out, 0.0)
+    rho_b = np.where(~red, rho_out if inside_red else rho_in, 0.0)
+    return rho_r.astype(np.float64), rho_b.astype(np.float64)
+
+
+def static_bubble(n=64, radius=16.0, A=1e-3, tau=1.0, beta=0.7, collision="bgk",
+                  storage="f32"):
+    """Static bubble, density and viscosity ratio 1: red disk of radius 16
+    centred in a 64 x 64 periodic blue lattice, A = 1e-3, beta = 0.7, tau = 1."""
+    p = params(nx=n, ny=n, tau_r=tau, tau_b=tau, A=A, beta=beta, collision=collision,
+               storage=storage)
+    rr, rb = disk_fields(n, n, n / 2, n / 2, radius, 1.0, 1.0)
+    return dict(name=f"static-bubble {n}x{n} R={radius:g}", params=p, rho_r=rr, rho_b=rb,
+                ux=None, uy=None, radius=radius, center=(n / 2, n / 2))
+
+
+def bubble_cell(gamma, M, radius, n=512, tau_min=0.6, sigma=4.0e-3 / 9.0, beta=0.7,
+                collision="bgk", storage="f32"):
+    """One cell of the bubble sweep.  The light fluid is inside and coloured
+    red (rho0_r = 1, rho0_b = gamma).  M is the dynamic-viscosity ratio
+    heavy/light, so nu_heavy / nu_light = M / gamma; the smaller tau is
+    ``tau_min``.  Surface tension is fixed through sigma (A follows omega)."""
+    ratio = M / gamma                       # nu_heavy / nu_light
+    if ratio <= 1.0:
+        tau_h = tau_min
+        tau_l = tau_from_nu(nu_from_tau(tau_h) / ratio)
+    else:
+        tau_l = tau_min
+        tau_h = tau_from_nu(nu_from_tau(tau_l) * ratio)
+    p = params(nx=n, ny=n, rho0_r=1.0, rho0_b=float(gamma), tau_r=tau_l, tau_b=tau_h,
+               sigma=sigma, beta=beta, collision=collision, storage=storage)
+    rr, rb = disk_fields(n, n, n / 2, n / 2, radius, 1.0, float(gamma))
+    return dict(name=f"bubble {n}x{n} gamma={gamma} M={M} R={radius}", params=p, rho_r=rr,
+                rho_b=rb, ux=None, uy=None, radius=float(radius), center=(n / 2, n / 2),
+                gamma=gamma, M=M)
+
+
+SWEEP_GAMMAS = (10, 100, 1000)
+SWEEP_MS = (1, 10, 100)
+
+
+def bubble_sweep(seed=0, n=512, storage="f32", collision="bgk"):
+    """The 3 x 3 sweep; radii drawn uniformly from {64..128} with ``seed``."""
+    rng = np.random.default_rng(seed)
+    cells = []
+    for g in SWEEP_GAMMAS:
+        for m in SWEEP_MS:
+            r = int(rng.integers(64, 129))
+            cells.append(bubble_cell(g, m, r, n=n, storage=storage, collision=collision))
+    return cells
+
+
+def slug_bands(nx, rng, lo=200, hi=600):
+    """Alternating heavy/light bands along x with seeded lengths in [lo, hi];
+    the last band absorbs the remainder; an even count of at least two."""
+    edges = [0]
+    while True:
+        length = int(rng.integers(lo, hi + 1))
+        if edges[-1] + length >= nx:
+            break
+        edges.append(edges[-1] + length)
+    if len(edges) % 2 == 1 and len(edges) > 2:
+        edges.pop()                         # merge the last two bands
+    if len(edges) < 2:
+        edges = [0, nx // 2]
+    heavy = np.zeros(nx, dtype=bool)
+    for b, x0 in enumerate(edges):
+        x1 = edges[b + 1] if b + 1 < len(edges) else nx
+        heavy[x0:x1] = (b % 2 == 0)
+    return heavy
+
+
+def gravity_slug(seed=0, nx=4096, ny=256, gamma=10, Re=10, g=1e-6, A=1e-3, beta=0.7,
+                 storage="f32", collision="bgk", band_lo=200, band_hi=600):
+    """Periodic channel with walls top/bottom and a body force along +x.
+    Heavy (red, rho0_r = gamma) and light (blue) full-height slugs.  The heavy
+    viscosity follows Re = g H^3 / (8 nu_l^2) with H = ny; mu_g = mu_l / 2."""
+    rng = np.random.default_rng(seed)
+    nu_l = math.sqrt(g * ny ** 3 / (8.0 * Re))
+    nu_g = nu_l * gamma / 2.0
+    p = params(nx=nx, ny=ny, bc_x="periodic", bc_y="walls", rho0_r=float(gamma), rho0_b=1.0,
+               tau_r=tau_from_nu(nu_l), tau_b=tau_from_nu(nu_g), A=A, beta=beta, gx=g,
+               storage=storage, collision=collision)
+    heavy = slug_bands(nx, rng, band_lo, band_hi)
+    rr = np.where(heavy[None, :], float(gamma), 0.0) * np.ones((ny, 1))
+    rb = np.where(heavy[None, :], 0.0, 1.0) * np.ones((ny, 1))
+    return dict(name=f"gravity-slug {nx}x{ny} gamma={gamma} Re={Re}", params=p,
+                rho_r=rr.astype(np.float64), rho_b=rb.astype(np.float64), ux=None, uy=None)
+
+
+def inlet_schedule(total_steps, seed=0, lo=300, hi=800, first_red=True):
+    """Inlet colour segments: list of (start_step, colour) with seeded lengths."""
+    rng = np.random.default_rng(seed)
+    seg, t, red = [], 0, first_red
+    while t < total_steps:
+        seg.append((t, 1 if red else -1))
+        t += int(rng.integers(lo, hi + 1))
+        red = not red
+    return seg
+
+
+def inlet_outlet(seed=0, nx=8192, ny=512, gamma=100, M=10, u_in=0.01, A=1e-3, beta=0.7,
+                 tau_heavy=0.6, storage="f32", collision="bgk", total_steps=200000):
+    """Channel: west velocity inlet, east pressure outlet, walls top/bottom.
+    Heavy fluid red (rho0_r = gamma), light blue.  nu_heavy/nu_light = M/gamma;
+    tau_heavy = 0.6.  Initial fill: light fluid at rest.  The outlet pressure
+    is the common reference pressure of the two fluids, written here as the
+    light fluid's rho0 times its squared sound speed 3 (1 - alpha_light) / 5."""
+    nu_h = nu_from_tau(tau_heavy)
+    nu_l = nu_h * gamma / M
+    p0 = 0.48   # rho0_light * 3 (1 - 0.2) / 5
+    p = params(nx=nx, ny=ny, bc_x="open", bc_y="walls", rho0_r=float(gamma), rho0_b=1.0,
+               tau_r=tau_heavy, tau_b=tau_from_nu(nu_l), A=A, beta=beta, u_in_r=u_in,
+               u_in_b=u_in, p_out=p0, storage=storage, collision=collision)
+    rr = np.zeros((ny, nx))
+    rb = np.ones((ny, nx))
+    return dict(name=f"inlet-outlet {nx}x{ny} gamma={gamma} M={M}", params=p, rho_r=rr,
+                rho_b=rb, ux=None, uy=None,
+                schedule=inlet_schedule(total_steps, seed=seed))
+
+
+def random_fields(nx, ny, seed=0, rho0_r=1.0, rho0_b=1.0, umax=0.02, smooth=True):
+    """Rough two-phase fields for parity tests: a seeded, smoothed random phase
+    indicator (with mixed interface nodes) and a small random velocity."""
+    rng = np.random.default_rng(seed)
+    f = rng.random((ny, nx))
+    if smooth:
+        for _ in range(3):
+            f = (f + np.roll(f, 1, 0) + np.roll(f, -1, 0) + np.roll(f, 1, 1) + np.roll(f, -1, 1)) / 5
+    f = np.clip((f - f.mean()) * 8 + 0.5, 0.0, 1.0)
+    rho_r = f * rho0_r
+    rho_b = (1.0 - f) * rho0_b
+    ux = (rng.random((ny, nx)) - 0.5) * 2 * umax
+    uy = (rng.random((ny, nx)) - 0.5) * 2 * umax
+    return rho_r, rho_b, ux, uy

@@ -1,0 +1,63 @@
+"""Pins of the seeded workload recipes (host logic, no GPU)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1903_01168_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_periodic_slug_tau_table():
+    """Re -> (tau_g, tau_l) of the paper's periodic slug case is reproduced by
+    the recipe used for the gravity-slug workload (nu_g = nu_l * gamma / 2)."""
+    rows = np.loadtxt(os.path.join(GOLD, "periodic_slug_tau.txt"))
+    g, H, gamma = 5.0e-7, 91, 5.0
+    for Re, tau_g, tau_l in rows:
+        nu_l = math.sqrt(g * H ** 3 / (8.0 * Re))
+        assert W.tau_from_nu(nu_l) == pytest.approx(tau_l, abs=6e-4)
+        assert W.tau_from_nu(nu_l * gamma / 2.0) == pytest.approx(tau_g, abs=1.1e-3)
+        case = W.gravity_slug(nx=64, ny=H, gamma=gamma, Re=Re, g=g, band_lo=10, band_hi=20)
+        assert case["params"]["tau_r"] == pytest.approx(tau_l, abs=6e-4)
+        assert case["params"]["tau_b"] == pytest.approx(tau_g, abs=1.1e-3)
+
+
+def test_static_bubble_geometry():
+    c = W.static_bubble()
+    rr, rb = c["rho_r"], c["rho_b"]
+    assert rr.shape == (64, 64)
+    assert np.all((rr == 1) ^ (rb == 1)) and np.all(rr + rb == 1)
+    # cell-centred disk: symmetric under transposition and mirrors
+    assert np.array_equal(rr, rr.T) and np.array_equal(rr, rr[::-1]) and np.array_equal(rr, rr[:, ::-1])
+    assert abs(rr.sum() - math.pi * 256) < 40
+
+
+def test_bubble_sweep_seeded():
+    a = W.bubble_sweep(seed=0, n=64)
+    b = W.bubble_sweep(seed=0, n=64)
+    c = W.bubble_sweep(seed=1, n=64)
+    assert [x["radius"] for x in a] == [x["radius"] for x in b]
+    assert [x["radius"] for x in a] != [x["radius"] for x in c]
+    assert len(a) == 9
+    for cell in a:
+        p = cell["params"]
+        assert 64 <= cell["radius"] <= 128
+        assert min(p["tau_r"], p["tau_b"]) == pytest.approx(0.6)
+        nu_l, nu_h = (p["tau_r"] - 0.5) / 3, (p["tau_b"] - 0.5) / 3
+        assert nu_h / nu_l == pytest.approx(cell["M"] / cell["gamma"])
+        assert p["rho0_b"] == cell["gamma"] and p["rho0_r"] == 1.0
+
+
+def test_slug_bands_and_schedule():
+    rng = np.random.default_rng(0)
+    heavy = W.slug_bands(4096, rng)
+    edges = np.flatnonzero(np.diff(heavy.astype(int))) + 1
+    bands = np.diff(np.concatenate([[0], edges, [4096]]))
+    assert len(bands) % 2 == 0 and len(bands) >= 2
+    assert np.all(bands[:-1] >= 200) and np.all(bands[:-1] <= 600)
+    sched = W.inlet_schedule(20000, seed=3)
+    starts = [s for s, _ in sched]
+    assert starts[0] == 0 and all(300 <= b - a <= 800 for a, b in zip(starts, starts[1:]))
+    assert all(c1 == -c2 for (_, c1), (_, c2) in zip(sched, sched[1:]))
