@@ -1,0 +1,170 @@
+/*
+ * cglbm.h -- C ABI of the MI355X colour-gradient lattice Boltzmann library.
+ *
+ * Method: two-population colour-gradient LBM on D2Q9 (Douillet-Grellier,
+ * Leclaire, Vidal, Bertrand, De Vuyst, arXiv:1903.01168, Sec. 2).  One time
+ * step = pull streaming (Sec. 2 eq. (subop4)) with periodic wrap, halfway
+ * bounce-back walls (Sec. 2.5 item 1) or two-phase Zou-He inlet/outlet
+ * (Sec. 2.5 item 3), colour-blind BGK or MRT collision with omega interpolated
+ * across the interface (Sec. 2.1.1-2.1.2), the surface-tension perturbation
+ * (Sec. 2.2) and the recolouring (Sec. 2.3).  Everything runs in hand-written
+ * HIP kernels for gfx950; host code only validates, plans and launches.
+ *
+ * General conventions
+ *  - Every function returns an int status: LBM_OK (0) or a negative LBM_E_*
+ *    code.  lbm_last_error(ctx) returns a message for the last failure on that
+ *    context (ctx may be NULL for failures of the create functions; that
+ *    message is per thread).  No C++ exception crosses this interface.
+ *  - Host arrays are FP64, caller-owned, row-major [ny][nx] with x fastest and
+ *    y pointing "north" (direction 2 of the lattice).
+ *  - Velocity numbering: 0 (0,0); 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1);
+ *    5 (1,1); 6 (-1,1); 7 (-1,-1); 8 (1,-1) -- the order of the rows of the
+ *    MRT matrix of Appendix B.
+ *  - A context owns one lattice, is bound to one HIP stream and one device
+ *    (the device current at creation), and is not thread-safe.  Calls on it
+ *    are asynchronous on its stream unless stated otherwise.
+ *  - The stored state is the population set after the recolouring of the last
+ *    step, about to be streamed; the initial state is the equilibrium of the
+ *    given fields.  "Fields at step n" are the moments of the streamed and
+ *    boundary-completed populations, i.e. what step n+1 collides.
+ */
+#ifndef CGLBM_H
+#define CGLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_E_INVAL (-1)    /* invalid argument or parameter combination        */
+#define LBM_E_NOMEM (-2)    /* device or host allocation failed                  */
+#define LBM_E_DEVICE (-3)   /* a HIP call failed (no device, launch failure ...) */
+#define LBM_E_UNSTABLE (-4) /* non-finite values seen by the diagnostics         */
+#define LBM_E_BUSY (-5)     /* request still running / capacity exhausted        */
+#define LBM_E_NOTFOUND (-6) /* unknown request id                                */
+
+/* Face boundary conditions.  x faces: both PERIODIC, or ZOUHE_VELOCITY on
+ * x-low with ZOUHE_PRESSURE on x-high.  y faces: both PERIODIC or both
+ * BOUNCEBACK (no-slip walls half-way outside the first/last row). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_ZOUHE_VELOCITY = 2, LBM_BC_ZOUHE_PRESSURE = 3 };
+enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
+/* Population storage.  Arithmetic is FP32 in every mode.  F16S / BF16S store
+ * each population as a 16-bit deviation (N/rho0_k - phi~_k,i) * 2^s from the
+ * rest state of its colour, phi~ being phi rounded to the 16-bit format. */
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16S = 1, LBM_STORE_BF16S = 2 };
+
+typedef struct {
+    int32_t nx, ny;                         /* lattice nodes, >= 1 (>= 2 along an open x) */
+    int32_t bc_xlo, bc_xhi, bc_ylo, bc_yhi; /* LBM_BC_*                                   */
+    int32_t collision;                      /* LBM_COLL_*                                 */
+    int32_t storage;                        /* LBM_STORE_*                                */
+    double rho0_r, rho0_b;   /* reference densities (> 0), Sec. 2.1.1                   */
+    double alpha_light;      /* alpha of the lighter fluid, 0 < a < 1 (0.2 in the paper) */
+    double tau_r, tau_b;     /* relaxation times (> 0.5); omega_k = 1/tau_k, Sec. 2.1.1  */
+    double delta;            /* width of the omega interpolation (> 0; 0.1)              */
+    double A;                /* perturbation amplitude, Sec. 2.2; or 0 with sigma > 0    */
+    double sigma;            /* surface tension: A(x) = 9 sigma omega_eff(x) / 4 if > 0  */
+    double beta;             /* recolouring parameter in [0, 1], Sec. 2.3                */
+    double mrt_lambda;       /* s_0..s_6 = lambda omega_eff (0.8), Sec. 2.1.2            */
+    double gx, gy;           /* body force per unit mass (Guo forcing)                   */
+    double u_in_r, u_in_b;   /* inlet x-velocity of red / blue inlet nodes               */
+    double p_out;            /* outlet pressure                                          */
+} lbm_params;
+
+typedef struct {
+    double mass_r, mass_b;   /* FP64 sums of rho_r and rho_b over the lattice            */
+    double area_r;           /* sum of (1 + psi) / 2: volume of the red fluid            */
+    double max_u;            /* max |u|                                                  */
+    double p_in, p_out;      /* mean pressure for r < r_in and r > r_out (see lbm_diag)  */
+    int64_t n_in, n_out;     /* node counts of those two regions                         */
+    int64_t n_nonfinite;     /* nodes with a non-finite density or velocity              */
+    int64_t step;            /* steps done                                               */
+} lbm_diag_t;
+
+typedef struct lbm_ctx lbm_ctx;
+
+const char *lbm_version(void);
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Device bytes a context needs for these parameters: two population buffers
+ * plus the field staging area.  Returns 0 for invalid parameters. */
+size_t lbm_bytes_required(const lbm_params *p);
+/* Bytes of one population buffer (18 planes, row pitch padded to 64 nodes). */
+size_t lbm_buffer_bytes(const lbm_params *p);
+
+/* Create a context on the current device.  hip_stream: a hipStream_t, or NULL
+ * for a stream owned by the context.  Device memory is allocated here. */
+int lbm_create(const lbm_params *p, void *hip_stream, lbm_ctx **out);
+/* Same, with two caller-owned device buffers of lbm_buffer_bytes(p) bytes
+ * each (256-byte aligned); they must outlive the context. */
+int lbm_create_ext(const lbm_params *p, void *hip_stream, void *buf_a, void *buf_b,
+                   size_t bytes_each, lbm_ctx **out);
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Equilibrium initialisation (Sec. 2.1.1 eq. (equilibrium)) from host fields;
+ * ux / uy may be NULL (zero).  Resets the step counter. */
+int lbm_init_fields(lbm_ctx *ctx, const double *rho_r, const double *rho_b, const double *ux,
+                    const double *uy);
+/* Inlet colour per row (+1 red, -1 blue), for LBM_BC_ZOUHE_VELOCITY (Sec. 2.5
+ * item 3).  Default: all red.  Takes effect for steps launched afterwards. */
+int lbm_set_inlet_color(lbm_ctx *ctx, const int8_t *color_y);
+
+/* Advance n >= 0 steps (asynchronous).  Long runs replay a captured HIP graph
+ * of a fixed number of steps. */
+int lbm_step(lbm_ctx *ctx, int64_t n);
+int64_t lbm_steps_done(const lbm_ctx *ctx);
+int lbm_sync(lbm_ctx *ctx);
+
+/* Fields at the current step into caller-owned host arrays (any may be NULL);
+ * p = sum_k rho_k c_s,k^2 (Sec. 2.1.1 eq. (pressureRelation)).  d (nullable)
+ * receives the FP64 diagnostics without the pressure regions.  Synchronises;
+ * returns LBM_E_UNSTABLE if a non-finite value was seen. */
+int lbm_moments(lbm_ctx *ctx, double *rho_r, double *rho_b, double *ux, double *uy, double *p,
+                lbm_diag_t *d);
+/* FP64 diagnostics computed on the device (deterministic reduction order).
+ * circle (nullable) = {cx, cy, r_in, r_out}: the mean pressure is taken over
+ * nodes whose cell centre (x+1/2, y+1/2) lies at r < r_in and r > r_out. */
+int lbm_diag(lbm_ctx *ctx, const double *circle, lbm_diag_t *d);
+
+/* Populations of the stored state, decoded to FP64, layout [2][9][ny][nx]
+ * (colour, direction, y, x); and the reverse (encoded to the storage type). */
+int lbm_get_pops(lbm_ctx *ctx, double *host);
+int lbm_set_pops(lbm_ctx *ctx, const double *host);
+
+/* Raw checkpoint of the stored state (bit-exact resume): header + both colour
+ * population planes in the storage format + the step counter.  *written
+ * receives the size; with host == NULL only the size is returned. */
+int lbm_save_state(lbm_ctx *ctx, void *host, size_t cap, size_t *written);
+int lbm_load_state(lbm_ctx *ctx, const void *host, size_t n);
+
+/* Launch-shape control (tuning): columns per workgroup (64, 128 or 256) and
+ * rows per workgroup strip (0 = automatic). */
+int lbm_set_launch(lbm_ctx *ctx, int32_t tile_x, int32_t strip_rows);
+/* The HIP stream of the context (a hipStream_t). */
+void *lbm_stream(const lbm_ctx *ctx);
+
+/* ---- batched stepping -------------------------------------------------
+ * A batch advances several contexts (same device, same storage type) with ONE
+ * kernel launch per time step: every workgroup finds its lattice in a device
+ * table of lattice descriptors.  Each lattice's arithmetic is exactly that of
+ * lbm_step, so results are bit-identical to stepping the contexts one by one.
+ * The contexts must not be stepped outside the batch while it exists
+ * (LBM_E_INVAL otherwise); lbm_moments / lbm_diag / checkpoints on them stay
+ * valid.  tile_x: 0 (automatic), 64, 128 or 256. */
+typedef struct lbm_batch lbm_batch;
+int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_stream, lbm_batch **out);
+int lbm_batch_step(lbm_batch *b, int64_t n);
+int lbm_batch_destroy(lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+
+/* Plain device-to-device copy of n bytes on the context stream (measures
+ * achievable HBM bandwidth beside the step). */
+int lbm_bw_copy(lbm_ctx *ctx, void *dst, const void *src, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

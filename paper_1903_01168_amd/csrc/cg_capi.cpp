@@ -1,0 +1,813 @@
+// cg_capi.cpp -- the C ABI of include/cglbm.h: validation, derived
+// constants, buffer ownership, launch planning, HIP-graph replay of long step
+// runs, moments/diagnostics and checkpoints.  All lattice arithmetic happens
+// in the kernels of cg_kernels.hip; this file only prepares and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cg_capi_internal.hpp"
+#include "cg_kernels.hpp"
+#include "cglbm.h"
+
+using cgd::SlotDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+    void *buf[2] = {nullptr, nullptr};
+    bool own_buf = false;
+    size_t buf_bytes = 0;
+    cgi::Layout lay{};
+    int8_t *d_inlet = nullptr;
+    SlotDesc desc{};
+    SlotDesc *d_desc = nullptr;
+    float *d_fields = nullptr;          // 5 n floats: init input / moments output
+    double *d_partial = nullptr;
+    double *d_out = nullptr;
+    int64_t steps = 0;
+    int tx = 0, strip_req = 0, tiles = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_len = 0;
+    std::string err;
+};
+
+namespace cgi {
+
+int fail(lbm_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    g_err = msg;
+    return code;
+}
+
+static int hip_fail(lbm_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int validate(const lbm_params *p, std::string &msg)
+{
+    if (!p) { msg = "params is NULL"; return LBM_E_INVAL; }
+    if (p->nx < 1 || p->ny < 1) { msg = "nx and ny must be >= 1"; return LBM_E_INVAL; }
+    {
+        // one colour half (9 planes) of a buffer must stay below 4 GiB: kernels
+        // address it with 32-bit buffer offsets
+        const long long pitch = (p->nx + 63) / 64 * 64;
+        const long long elem = p->storage == LBM_STORE_F32 ? 4 : 2;
+        if (9 * pitch * p->ny * elem >= (1LL << 32) - 4096) { msg = "lattice too large"; return LBM_E_INVAL; }
+    }
+    const bool xper = p->bc_xlo == LBM_BC_PERIODIC || p->bc_xhi == LBM_BC_PERIODIC;
+    if (xper && !(p->bc_xlo == LBM_BC_PERIODIC && p->bc_xhi == LBM_BC_PERIODIC)) {
+        msg = "a periodic x face must be paired with a periodic x face"; return LBM_E_INVAL;
+    }
+    if (!xper && !(p->bc_xlo == LBM_BC_ZOUHE_VELOCITY && p->bc_xhi == LBM_BC_ZOUHE_PRESSURE)) {
+        msg = "x faces: both periodic, or velocity inlet at x-low with pressure outlet at x-high"; return LBM_E_INVAL;
+    }
+    if (!xper && p->nx < 2) { msg = "an open x direction needs nx >= 2"; return LBM_E_INVAL; }
+    const bool yper = p->bc_ylo == LBM_BC_PERIODIC && p->bc_yhi == LBM_BC_PERIODIC;
+    const bool ywall = p->bc_ylo == LBM_BC_BOUNCEBACK && p->bc_yhi == LBM_BC_BOUNCEBACK;
+    if (!yper && !ywall) { msg = "y faces: both periodic or both bounce-back"; return LBM_E_INVAL; }
+    if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_MRT) { msg = "unknown collision"; return LBM_E_INVAL; }
+    if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16S) { msg = "unknown storage"; return LBM_E_INVAL; }
+    if (!(p->rho0_r > 0 && p->rho0_b > 0)) { msg = "rho0 must be > 0"; return LBM_E_INVAL; }
+    if (!(p->alpha_light > 0 && p->alpha_light < 1)) { msg = "alpha_light must be in (0, 1)"; return LBM_E_INVAL; }
+    if (!(p->tau_r > 0.5 && p->tau_b > 0.5)) { msg = "tau must be > 0.5"; return LBM_E_INVAL; }
+    if (!(p->delta > 0)) { msg = "delta must be > 0"; return LBM_E_INVAL; }
+    if ((p->A > 0) == (p->sigma > 0) && !(p->A == 0 && p->sigma == 0)) {
+        msg = "give exactly one of A and sigma (or both zero)"; return LBM_E_INVAL;
+    }
+    if (p->A < 0 || p->sigma < 0) { msg = "A and sigma must be >= 0"; return LBM_E_INVAL; }
+    if (!(p->beta >= 0 && p->beta <= 1)) { msg = "beta must be in [0, 1]"; return LBM_E_INVAL; }
+    if (p->collision == LBM_COLL_MRT && !(p->mrt_lambda > 0 && p->mrt_lambda < 2 * p->tau_r && p->mrt_lambda < 2 * p->tau_b)) {
+        msg = "mrt_lambda must be > 0 and keep lambda*omega < 2"; return LBM_E_INVAL;
+    }
+    if (!xper && !(p->p_out > 0)) { msg = "p_out must be > 0 with an open outlet"; return LBM_E_INVAL; }
+    if (!xper && !(std::fabs(p->u_in_r) < 1 && std::fabs(p->u_in_b) < 1)) { msg = "|u_in| must be < 1"; return LBM_E_INVAL; }
+    if (!std::isfinite(p->gx) || !std::isfinite(p->gy)) { msg = "non-finite body force"; return LBM_E_INVAL; }
+    return LBM_OK;
+}
+
+Layout layout(const lbm_params *p)
+{
+    Layout L;
+    L.elem = p->storage == LBM_STORE_F32 ? 4 : 2;
+    L.pitch = (p->nx + 63) / 64 * 64;
+    L.plane = (long long)L.pitch * p->ny;
+    L.buf_bytes = (size_t)L.plane * 18 * L.elem;
+    return L;
+}
+
+static float round_to_storage(double v, int storage)
+{
+    if (storage == LBM_STORE_F16S) return (float)(_Float16)(float)v;
+    if (storage == LBM_STORE_BF16S) {
+        float f = (float)v;
+        uint32_t b;
+        std::memcpy(&b, &f, 4);
+        b += 0x7fffu + ((b >> 16) & 1u);
+        b &= 0xffff0000u;
+        std::memcpy(&f, &b, 4);
+        return f;
+    }
+    return (float)v;
+}
+
+// Derived constants of Sec. 2.1.1 (alpha from equal reference pressures,
+// c_s^2 = 3 (1 - alpha) / 5, phi by class, omega interpolation) and of the
+// storage codec.  Pointers, geometry and tiling are filled by the caller.
+void fill_desc(const lbm_params *p, SlotDesc &d)
+{
+    const double ar = p->rho0_r <= p->rho0_b ? p->alpha_light : 1.0 - (1.0 - p->alpha_light) * p->rho0_b / p->rho0_r;
+    const double ab = p->rho0_r <= p->rho0_b ? 1.0 - (1.0 - p->alpha_light) * p->rho0_r / p->rho0_b : p->alpha_light;
+    const double alpha[2] = {ar, ab};
+    const double rho0[2] = {p->rho0_r, p->rho0_b};
+    const int s_shift = p->storage == LBM_STORE_F16S ? 12 : 0;
+    const double two_s = std::ldexp(1.0, s_shift);
+    for (int k = 0; k < 2; ++k) {
+        const double ph[3] = {alpha[k], (1.0 - alpha[k]) / 5.0, (1.0 - alpha[k]) / 20.0};
+        d.rho0[k] = (float)rho0[k];
+        d.inv_rho0[k] = (float)(1.0 / rho0[k]);
+        d.cs2[k] = (float)(3.0 * (1.0 - alpha[k]) / 5.0);
+        d.rho_out[k] = (float)(p->p_out / (3.0 * (1.0 - alpha[k]) / 5.0));
+        d.enc_scale[k] = (float)(two_s / rho0[k]);
+        // FP32 weights; the residual of their unit sum is carried separately so
+        // that the equilibrium holds exactly the node's mass (no drift per step)
+        const float f1 = (float)ph[1], f2 = (float)ph[2];
+        const float f0 = (float)(1.0 - 4.0 * (double)f1 - 4.0 * (double)f2);
+        d.phi0_eps[k] = (float)(1.0 - (double)f0 - 4.0 * (double)f1 - 4.0 * (double)f2);
+        const float fc[3] = {f0, f1, f2};
+        for (int c = 0; c < 3; ++c) {
+            d.phi[k][c] = fc[c];
+            const float pt = round_to_storage(ph[c], p->storage);
+            d.phit[k][c] = p->storage == LBM_STORE_F32 ? 0.f : pt;
+            d.enc_off[k][c] = p->storage == LBM_STORE_F32 ? 0.f : (float)(pt * two_s);
+        }
+    }
+    d.dec_mul = (float)(1.0 / two_s);
+    const double wr = 1.0 / p->tau_r, wb = 1.0 / p->tau_b, del = p->delta;
+    const double chi = 2.0 * wr * wb / (wr + wb);
+    const double eta = 2.0 * (wr - chi) / del;
+    const double lam = 2.0 * (chi - wb) / del;
+    d.omega_r = (float)wr;
+    d.omega_b = (float)wb;
+    d.chi = (float)chi;
+    d.eta = (float)eta;
+    d.kappa = (float)(-eta / (2.0 * del));
+    d.lam = (float)lam;
+    d.nu = (float)(lam / (2.0 * del));
+    d.delta = (float)del;
+    d.A = (float)p->A;
+    d.sigma94 = (float)(9.0 * p->sigma / 4.0);
+    d.beta = (float)p->beta;
+    d.mrt_lambda = (float)p->mrt_lambda;
+    d.gx = (float)p->gx;
+    d.gy = (float)p->gy;
+    d.u_in[0] = (float)p->u_in_r;
+    d.u_in[1] = (float)p->u_in_b;
+    int f = 0;
+    if (p->bc_xlo == LBM_BC_PERIODIC) f |= cgd::F_XPER;
+    else f |= cgd::F_XOPEN;
+    if (p->bc_ylo == LBM_BC_PERIODIC) f |= cgd::F_YPER;
+    if (p->collision == LBM_COLL_MRT) f |= cgd::F_MRT;
+    if (p->sigma > 0) f |= cgd::F_SIGMA;
+    if (p->gx != 0.0 || p->gy != 0.0) f |= cgd::F_FORCE;
+    d.flags = f;
+}
+
+int default_tx(int nx) { return nx >= 256 ? 256 : (nx >= 128 ? 128 : 64); }
+
+// A wavefront writes 60 columns (it reads 2 more on each side).
+static const int kWaveCols = 60;
+
+static int wave_tiles(int nx) { return (nx + kWaveCols - 1) / kWaveCols; }
+
+int plan_strip(int nx, int ny, int tx, int req)
+{
+    (void)tx;
+    if (req > 0) return req < ny ? req : ny;
+    const long long waves_per_row = wave_tiles(nx);
+    // aim at ~16K waves in flight (64 per CU), strips of 4..64 rows
+    long long strip = (waves_per_row * ny + 16383) / 16384;
+    if (strip < 4) strip = 4;
+    if (strip > 64) strip = 64;
+    if (strip > ny) strip = ny;
+    return (int)strip;
+}
+
+void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip)
+{
+    d.nx = p->nx;
+    d.ny = p->ny;
+    d.pitch = L.pitch;
+    d.plane = L.plane;
+    d.strip = strip;
+    const int waves = tx / 64;
+    d.tiles_x = (wave_tiles(p->nx) + waves - 1) / waves;   // workgroups across x
+    d.tiles_y = (p->ny + strip - 1) / strip;
+}
+
+}  // namespace cgi
+
+using namespace cgi;
+
+static int upload_desc(lbm_ctx *c)
+{
+    hipError_t e = hipMemcpyAsync(c->d_desc, &c->desc, sizeof(SlotDesc), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(c, e, "uploading the lattice descriptor");
+}
+
+static void drop_graphs(lbm_ctx *c)
+{
+    for (auto &g : c->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+static int replan(lbm_ctx *c)
+{
+    const int tx = c->tx ? c->tx : default_tx(c->p.nx);
+    const int strip = plan_strip(c->p.nx, c->p.ny, tx, c->strip_req);
+    set_geometry(c->desc, &c->p, c->lay, tx, strip);
+    c->desc.tile_begin = 0;
+    c->desc.active_steps = INT_MAX;
+    c->tiles = c->desc.tiles_x * c->desc.tiles_y;
+    c->tx = tx;
+    drop_graphs(c);
+    return upload_desc(c);
+}
+
+extern "C" {
+
+const char *lbm_version(void) { return "cglbm 0.1 (gfx950, HIP)"; }
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+size_t lbm_buffer_bytes(const lbm_params *p)
+{
+    std::string m;
+    if (validate(p, m) != LBM_OK) return 0;
+    return layout(p).buf_bytes;
+}
+
+size_t lbm_bytes_required(const lbm_params *p)
+{
+    std::string m;
+    if (validate(p, m) != LBM_OK) return 0;
+    const Layout L = layout(p);
+    const size_t n = (size_t)p->nx * p->ny;
+    return 2 * L.buf_bytes + 5 * n * sizeof(float) + (size_t)p->ny + sizeof(SlotDesc) +
+           (size_t)(cgd::moments_blocks((long long)n) * 9 + 9) * sizeof(double);
+}
+
+static int create_common(const lbm_params *p, void *stream, void *ba, void *bb, size_t bytes_each, lbm_ctx **out)
+{
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    std::string msg;
+    int rc = validate(p, msg);
+    if (rc != LBM_OK) return fail(nullptr, rc, msg);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(nullptr, LBM_E_DEVICE, "no HIP device available");
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    c->p = *p;
+    (void)hipGetDevice(&c->device);
+    c->lay = layout(p);
+    c->buf_bytes = c->lay.buf_bytes;
+    const size_t n = (size_t)p->nx * p->ny;
+
+    auto bail = [&](int code, const std::string &m) {
+        lbm_destroy(c);
+        return fail(nullptr, code, m);
+    };
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess)
+            return bail(LBM_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        c->own_stream = true;
+    }
+    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return bail(LBM_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    if (ba || bb) {
+        if (!ba || !bb || bytes_each < c->buf_bytes)
+            return bail(LBM_E_INVAL, "external buffers: both needed, each of lbm_buffer_bytes() bytes");
+        if (((uintptr_t)ba | (uintptr_t)bb) & 255u) return bail(LBM_E_INVAL, "external buffers must be 256-byte aligned");
+        c->buf[0] = ba;
+        c->buf[1] = bb;
+    } else {
+        for (int k = 0; k < 2; ++k)
+            if (hipMalloc(&c->buf[k], c->buf_bytes) != hipSuccess) {
+                c->buf[k] = nullptr;
+                return bail(LBM_E_NOMEM, "hipMalloc of the population buffers failed");
+            }
+        c->own_buf = true;
+    }
+    const int nb = cgd::moments_blocks((long long)n);
+    if (hipMalloc(&c->d_fields, 5 * n * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_partial, (size_t)nb * 9 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_out, 9 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_inlet, (size_t)p->ny) != hipSuccess ||
+        hipMalloc(&c->d_desc, sizeof(SlotDesc)) != hipSuccess)
+        return bail(LBM_E_NOMEM, "hipMalloc of the work buffers failed");
+    std::vector<int8_t> red((size_t)p->ny, 1);
+    if ((e = hipMemcpy(c->d_inlet, red.data(), red.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(LBM_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    fill_desc(p, c->desc);
+    c->desc.buf[0] = c->buf[0];
+    c->desc.buf[1] = c->buf[1];
+    c->desc.inlet_color = c->d_inlet;
+    if ((rc = replan(c)) != LBM_OK) {
+        std::string m = c->err;
+        return bail(rc, m);
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_params *p, void *hip_stream, lbm_ctx **out)
+{
+    return create_common(p, hip_stream, nullptr, nullptr, 0, out);
+}
+
+int lbm_create_ext(const lbm_params *p, void *hip_stream, void *buf_a, void *buf_b, size_t bytes_each, lbm_ctx **out)
+{
+    if (!buf_a || !buf_b) return fail(nullptr, LBM_E_INVAL, "external buffers are NULL");
+    return create_common(p, hip_stream, buf_a, buf_b, bytes_each, out);
+}
+
+int lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return LBM_OK;
+    DeviceGuard g(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->own_buf)
+        for (auto &b : c->buf)
+            if (b) (void)hipFree(b);
+    if (c->d_fields) (void)hipFree(c->d_fields);
+    if (c->d_partial) (void)hipFree(c->d_partial);
+    if (c->d_out) (void)hipFree(c->d_out);
+    if (c->d_inlet) (void)hipFree(c->d_inlet);
+    if (c->d_desc) (void)hipFree(c->d_desc);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx *c, int32_t tile_x, int32_t strip_rows)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256)
+        return fail(c, LBM_E_INVAL, "tile_x must be 0, 64, 128 or 256");
+    if (strip_rows < 0) return fail(c, LBM_E_INVAL, "strip_rows must be >= 0");
+    DeviceGuard g(c->device);
+    c->tx = tile_x;
+    c->strip_req = strip_rows;
+    return replan(c);
+}
+
+void *lbm_stream(const lbm_ctx *c) { return c ? (void *)c->stream : nullptr; }
+
+int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
+
+int lbm_init_fields(lbm_ctx *c, const double *rho_r, const double *rho_b, const double *ux, const double *uy)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!rho_r || !rho_b) return fail(c, LBM_E_INVAL, "rho_r and rho_b are required");
+    DeviceGuard g(c->device);
+    const size_t n = (size_t)c->p.nx * c->p.ny;
+    std::vector<float> h(4 * n);
+    for (size_t i = 0; i < n; ++i) {
+        if (!(rho_r[i] >= 0) || !(rho_b[i] >= 0) || !(rho_r[i] + rho_b[i] > 0))
+            return fail(c, LBM_E_INVAL, "densities must be >= 0 with a positive sum at every node");
+        h[i] = (float)rho_r[i];
+        h[n + i] = (float)rho_b[i];
+        h[2 * n + i] = ux ? (float)ux[i] : 0.f;
+        h[3 * n + i] = uy ? (float)uy[i] : 0.f;
+    }
+    hipError_t e = hipMemcpyAsync(c->d_fields, h.data(), 4 * n * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = cgd::launch_init(c->p.storage, c->d_desc, (long long)n, c->d_fields, 0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);   // h is freed on return
+    if (e != hipSuccess) return hip_fail(c, e, "init");
+    c->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_set_inlet_color(lbm_ctx *c, const int8_t *color_y)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!color_y) return fail(c, LBM_E_INVAL, "color_y is NULL");
+    DeviceGuard g(c->device);
+    std::vector<int8_t> v(color_y, color_y + c->p.ny);
+    for (auto &x : v)
+        if (x != 1 && x != -1) return fail(c, LBM_E_INVAL, "inlet colours must be +1 or -1");
+    hipError_t e = hipMemcpyAsync(c->d_inlet, v.data(), v.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(c, e, "inlet colour upload");
+}
+
+static const int kGraphSteps = 32;   // steps per captured graph (even)
+
+static int build_graph(lbm_ctx *c, int parity)
+{
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
+        le = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (parity + j) & 1, 0, c->cap_stream);
+    e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(c, le != hipSuccess ? le : e, "graph capture");
+    }
+    e = hipGraphInstantiate(&c->graph[parity], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->graph[parity] = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (n < 0) return fail(c, LBM_E_INVAL, "n must be >= 0");
+    DeviceGuard g(c->device);
+    while (n >= 2 * kGraphSteps) {
+        const int par = (int)(c->steps & 1);
+        if (!c->graph[par]) {
+            int rc = build_graph(c, par);
+            if (rc != LBM_OK) return rc;
+        }
+        hipError_t e = hipGraphLaunch(c->graph[par], c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+        c->steps += kGraphSteps;
+        n -= kGraphSteps;
+    }
+    for (; n > 0; --n) {
+        hipError_t e = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (int)(c->steps & 1), 0, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        c->steps++;
+    }
+    return LBM_OK;
+}
+
+int lbm_sync(lbm_ctx *c)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    DeviceGuard g(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(c, e, "hipStreamSynchronize");
+}
+
+static int run_moments(lbm_ctx *c, bool fields, const double *circle, double *out9)
+{
+    const long long n = (long long)c->p.nx * c->p.ny;
+    hipError_t e = cgd::launch_moments(c->p.storage, c->d_desc, n, (int)(c->steps & 1), fields ? c->d_fields : nullptr,
+                                       c->d_partial, c->d_out, circle, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out9, c->d_out, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "moments");
+    return LBM_OK;
+}
+
+static void to_diag(const lbm_ctx *c, const double *o, lbm_diag_t *d)
+{
+    d->mass_r = o[0];
+    d->mass_b = o[1];
+    d->area_r = o[2];
+    d->p_in = o[4] > 0 ? o[3] / o[4] : 0.0;
+    d->n_in = (int64_t)o[4];
+    d->p_out = o[6] > 0 ? o[5] / o[6] : 0.0;
+    d->n_out = (int64_t)o[6];
+    d->n_nonfinite = (int64_t)o[7];
+    d->max_u = o[8];
+    d->step = c->steps;
+}
+
+int lbm_moments(lbm_ctx *c, double *rho_r, double *rho_b, double *ux, double *uy, double *p, lbm_diag_t *d)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    DeviceGuard g(c->device);
+    const size_t n = (size_t)c->p.nx * c->p.ny;
+    double o[9];
+    int rc = run_moments(c, true, nullptr, o);
+    if (rc != LBM_OK) return rc;
+    std::vector<float> h(5 * n);
+    hipError_t e = hipMemcpyAsync(h.data(), c->d_fields, 5 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "moments copy");
+    double *dst[5] = {rho_r, rho_b, ux, uy, p};
+    for (int f = 0; f < 5; ++f)
+        if (dst[f])
+            for (size_t i = 0; i < n; ++i) dst[f][i] = (double)h[f * n + i];
+    if (d) to_diag(c, o, d);
+    if (o[7] > 0) return fail(c, LBM_E_UNSTABLE, "non-finite values in the lattice");
+    return LBM_OK;
+}
+
+int lbm_diag(lbm_ctx *c, const double *circle, lbm_diag_t *d)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!d) return fail(c, LBM_E_INVAL, "d is NULL");
+    DeviceGuard g(c->device);
+    double o[9];
+    int rc = run_moments(c, false, circle, o);
+    if (rc != LBM_OK) return rc;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diag");
+    to_diag(c, o, d);
+    if (o[7] > 0) return fail(c, LBM_E_UNSTABLE, "non-finite values in the lattice");
+    return LBM_OK;
+}
+
+static int pops_io(lbm_ctx *c, double *out, const double *in)
+{
+    DeviceGuard g(c->device);
+    const size_t n = (size_t)c->p.nx * c->p.ny;
+    float *tmp = nullptr;
+    if (hipMalloc(&tmp, 18 * n * sizeof(float)) != hipSuccess) return fail(c, LBM_E_NOMEM, "hipMalloc failed");
+    std::vector<float> h(18 * n);
+    hipError_t e = hipSuccess;
+    const int which = (int)(c->steps & 1);
+    if (out) {
+        e = cgd::launch_pops(c->p.storage, c->d_desc, (long long)n, which, tmp, true, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), tmp, h.size() * 4, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            for (size_t i = 0; i < h.size(); ++i) out[i] = h[i];
+    } else {
+        for (size_t i = 0; i < h.size(); ++i) h[i] = (float)in[i];
+        e = hipMemcpyAsync(tmp, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = cgd::launch_pops(c->p.storage, c->d_desc, (long long)n, which, tmp, false, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(tmp);
+    return e == hipSuccess ? LBM_OK : hip_fail(c, e, "population copy");
+}
+
+int lbm_get_pops(lbm_ctx *c, double *host)
+{
+    if (!c || !host) return fail(c, LBM_E_INVAL, "NULL argument");
+    return pops_io(c, host, nullptr);
+}
+
+int lbm_set_pops(lbm_ctx *c, const double *host)
+{
+    if (!c || !host) return fail(c, LBM_E_INVAL, "NULL argument");
+    return pops_io(c, nullptr, host);
+}
+
+struct StateHeader {
+    char magic[8];
+    int32_t version, nx, ny, storage, pitch, pad;
+    int64_t steps;
+    uint64_t bytes;
+};
+
+int lbm_save_state(lbm_ctx *c, void *host, size_t cap, size_t *written)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const size_t total = sizeof(StateHeader) + c->buf_bytes;
+    if (written) *written = total;
+    if (!host) return LBM_OK;
+    if (cap < total) return fail(c, LBM_E_INVAL, "buffer too small");
+    DeviceGuard g(c->device);
+    StateHeader h{};
+    std::memcpy(h.magic, "CGLBMST1", 8);
+    h.version = 1;
+    h.nx = c->p.nx;
+    h.ny = c->p.ny;
+    h.storage = c->p.storage;
+    h.pitch = c->lay.pitch;
+    h.steps = c->steps;
+    h.bytes = c->buf_bytes;
+    std::memcpy(host, &h, sizeof h);
+    hipError_t e = hipMemcpyAsync((char *)host + sizeof h, c->buf[c->steps & 1], c->buf_bytes, hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(c, e, "save");
+}
+
+int lbm_load_state(lbm_ctx *c, const void *host, size_t n)
+{
+    if (!c || !host) return fail(c, LBM_E_INVAL, "NULL argument");
+    StateHeader h;
+    if (n < sizeof h) return fail(c, LBM_E_INVAL, "state too short");
+    std::memcpy(&h, host, sizeof h);
+    if (std::memcmp(h.magic, "CGLBMST1", 8) != 0 || h.version != 1) return fail(c, LBM_E_INVAL, "not a state blob");
+    if (h.nx != c->p.nx || h.ny != c->p.ny || h.storage != c->p.storage || h.pitch != c->lay.pitch ||
+        h.bytes != c->buf_bytes || n < sizeof h + c->buf_bytes)
+        return fail(c, LBM_E_INVAL, "state does not match this lattice");
+    DeviceGuard g(c->device);
+    hipError_t e = hipMemcpyAsync(c->buf[h.steps & 1], (const char *)host + sizeof h, c->buf_bytes,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "load");
+    c->steps = h.steps;
+    return LBM_OK;
+}
+
+int lbm_bw_copy(lbm_ctx *c, void *dst, const void *src, size_t n)
+{
+    if (!c || !dst || !src) return fail(c, LBM_E_INVAL, "NULL argument");
+    DeviceGuard g(c->device);
+    hipError_t e = cgd::launch_copy(dst, src, n, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(c, e, "copy");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch --
+struct lbm_batch {
+    std::vector<lbm_ctx *> ctx;
+    std::vector<int64_t> base;          // ctx step counter at creation
+    std::vector<SlotDesc> slots;
+    SlotDesc *d_slots = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int device = 0, storage = 0, tx = 0, tiles = 0;
+    int64_t steps = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+static int bfail(lbm_batch *b, int code, const std::string &m)
+{
+    if (b) b->err = m;
+    return fail(nullptr, code, m);
+}
+
+extern "C" {
+
+const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : lbm_last_error(nullptr); }
+
+int lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return LBM_OK;
+    DeviceGuard g(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto &x : b->graph)
+        if (x) (void)hipGraphExecDestroy(x);
+    if (b->d_slots) (void)hipFree(b->d_slots);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return LBM_OK;
+}
+
+int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_stream, lbm_batch **out)
+{
+    if (!out || !ctxs || n < 1) return fail(nullptr, LBM_E_INVAL, "batch: need at least one context");
+    *out = nullptr;
+    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256)
+        return fail(nullptr, LBM_E_INVAL, "tile_x must be 0, 64, 128 or 256");
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(nullptr, LBM_E_INVAL, "batch: NULL context");
+        if (ctxs[i]->device != ctxs[0]->device || ctxs[i]->p.storage != ctxs[0]->p.storage)
+            return fail(nullptr, LBM_E_INVAL, "batch: contexts must share device and storage type");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(nullptr, LBM_E_INVAL, "batch: a context appears twice");
+    }
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    b->device = ctxs[0]->device;
+    b->storage = ctxs[0]->p.storage;
+    DeviceGuard g(b->device);
+    int tx = tile_x;
+    if (!tx) {
+        tx = 256;
+        for (int i = 0; i < n; ++i) tx = std::min(tx, default_tx(ctxs[i]->p.nx));
+    }
+    b->tx = tx;
+    long long tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx *c = ctxs[i];
+        SlotDesc d = c->desc;
+        set_geometry(d, &c->p, c->lay, tx, plan_strip(c->p.nx, c->p.ny, tx, c->strip_req));
+        d.tile_begin = (int)tiles;
+        d.active_steps = INT_MAX;
+        if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer
+        tiles += (long long)d.tiles_x * d.tiles_y;
+        b->slots.push_back(d);
+        b->ctx.push_back(c);
+        b->base.push_back(c->steps);
+    }
+    if (tiles > INT_MAX / 2) {
+        lbm_batch_destroy(b);
+        return fail(nullptr, LBM_E_INVAL, "batch too large");
+    }
+    b->tiles = (int)tiles;
+    hipError_t e;
+    if (hip_stream) b->stream = (hipStream_t)hip_stream;
+    else b->stream = ctxs[0]->stream;
+    if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipMalloc(&b->d_slots, b->slots.size() * sizeof(SlotDesc))) != hipSuccess) {
+        b->d_slots = nullptr;
+        lbm_batch_destroy(b);
+        return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+    }
+    // the contexts' pending work must finish before the batch stream uses their buffers
+    for (auto *c : b->ctx) (void)hipStreamSynchronize(c->stream);
+    e = hipMemcpy(b->d_slots, b->slots.data(), b->slots.size() * sizeof(SlotDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        lbm_batch_destroy(b);
+        return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+static int batch_graph(lbm_batch *b, int parity)
+{
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+    hipError_t le = hipSuccess;
+    for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
+        le = cgd::launch_step(b->storage, b->tx, b->d_slots, (int)b->slots.size(), b->tiles, (parity + j) & 1, 0,
+                              b->cap_stream);
+    e = hipStreamEndCapture(b->cap_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return bfail(b, LBM_E_DEVICE, std::string("capture: ") + hipGetErrorString(le != hipSuccess ? le : e));
+    }
+    e = hipGraphInstantiate(&b->graph[parity], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        b->graph[parity] = nullptr;
+        return bfail(b, LBM_E_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t n)
+{
+    if (!b) return fail(nullptr, LBM_E_INVAL, "batch is NULL");
+    if (n < 0) return bfail(b, LBM_E_INVAL, "n must be >= 0");
+    for (size_t i = 0; i < b->ctx.size(); ++i)
+        if (b->ctx[i]->steps - b->base[i] != b->steps)
+            return bfail(b, LBM_E_INVAL, "a context of the batch was stepped outside it");
+    DeviceGuard g(b->device);
+    auto advance = [&](int64_t k) {
+        b->steps += k;
+        for (auto *c : b->ctx) c->steps += k;
+    };
+    while (n >= 2 * kGraphSteps) {
+        const int par = (int)(b->steps & 1);
+        if (!b->graph[par]) {
+            int rc = batch_graph(b, par);
+            if (rc != LBM_OK) return rc;
+        }
+        hipError_t e = hipGraphLaunch(b->graph[par], b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+        advance(kGraphSteps);
+        n -= kGraphSteps;
+    }
+    for (; n > 0; --n) {
+        hipError_t e = cgd::launch_step(b->storage, b->tx, b->d_slots, (int)b->slots.size(), b->tiles,
+                                        (int)(b->steps & 1), 0, b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+        advance(1);
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

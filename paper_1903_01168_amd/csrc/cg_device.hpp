@@ -1,0 +1,526 @@
+// cg_device.hpp -- device-side building blocks of the colour-gradient step:
+// lattice constants, the per-lattice descriptor, the population codecs, the
+// pull gather with boundary completion, and the node collision.
+//
+// Paper: arXiv:1903.01168, Sec. 2 (LBM immiscible multiphase model).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cgd {
+
+// ---------------------------------------------------------------- lattice --
+// D2Q9 in the order of the rows of the MRT matrix (Appendix B): 1..4 axis,
+// 5..8 diagonal.  All loops over directions are unrolled, so these fold.
+__host__ __device__ constexpr int cx(int i)
+{
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int i)
+{
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5); }
+__host__ __device__ constexpr int vclass(int i) { return i == 0 ? 0 : (i <= 4 ? 1 : 2); }
+// D2Q9 weights W (Sec. 2.1.1) and perturbation coefficients B (Sec. 2.2) by class
+__host__ __device__ constexpr float wgt(int i) { return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f); }
+__host__ __device__ constexpr float bco(int i) { return i == 0 ? -4.0f / 27.0f : (i <= 4 ? 2.0f / 27.0f : 5.0f / 108.0f); }
+
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "axis opposites");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
+
+enum : int { F_XPER = 1, F_XOPEN = 2, F_YPER = 4, F_MRT = 8, F_SIGMA = 16, F_FORCE = 32 };
+enum : int { ST_F32 = 0, ST_F16S = 1, ST_BF16S = 2 };
+
+// ------------------------------------------------------------- descriptor --
+// One lattice ("slot") of a launch.  Built on the host; read with scalar loads.
+struct SlotDesc {
+    void *buf[2];                 // population buffers; a launch reads buf[parity]
+    const int8_t *inlet_color;    // [ny], +1 red / -1 blue (open x only)
+    long long plane;              // elements between two of the 18 planes
+    int nx, ny, pitch;            // lattice size, row pitch in elements
+    int strip, tiles_x, tiles_y;  // rows per workgroup strip, tile grid
+    int tile_begin;               // first tile of this slot in the launch
+    int active_steps;             // launches with index >= this leave the slot alone
+    int flags;                    // F_*
+    int pad0;
+    float inv_rho0[2];            // 1 / rho0_k (colour field)
+    float rho0[2];
+    float phi[2][3];              // phi^k by class (equilibrium rest part)
+    float phi0_eps[2];            // 1 - (phi_0 + 4 phi_1 + 4 phi_2) of the FP32 values
+    float omega_r, omega_b;       // 1 / tau_k
+    float chi, eta, kappa, lam, nu, delta;  // omega_eff interpolation
+    float A, sigma94;             // constant A, or 9 sigma / 4 (F_SIGMA)
+    float beta, mrt_lambda;
+    float gx, gy;
+    float u_in[2];                // inlet velocity by colour
+    float rho_out[2];             // p_out / c_s,k^2
+    float cs2[2];
+    float enc_scale[2];           // 2^s / rho0_k            (16-bit storage)
+    float enc_off[2][3];          // phi~ 2^s by class
+    float dec_mul;                // 2^-s
+    float phit[2][3];             // phi~ by class
+};
+
+// ------------------------------------------------------------------ codec --
+// Populations are read and written with raw buffer instructions: one buffer
+// resource per colour half of a buffer (9 planes; offsets are 32-bit and a
+// resource bounds every access, so a stray offset reads 0 / drops the store
+// instead of faulting), a per-lane column offset and a scalar plane + row
+// offset.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+// Cache policy bits of the population loads and stores (0: default; the
+// non-temporal bit (2) measured slower for this access pattern).
+#ifndef CG_LOAD_POLICY
+#define CG_LOAD_POLICY 0
+#endif
+#ifndef CG_STORE_POLICY
+#define CG_STORE_POLICY 0
+#endif
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int ST> struct Codec;
+
+template <> struct Codec<ST_F32> {
+    using Raw = uint32_t;
+    static constexpr int bytes = 4;
+    static __device__ __forceinline__ Raw load(Rsrc r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, CG_LOAD_POLICY);
+    }
+    static __device__ __forceinline__ float dec(Raw v, const SlotDesc &, int, int) { return __uint_as_float(v); }
+    static __device__ __forceinline__ void store(float v, Rsrc r, uint32_t voff, uint32_t soff, const SlotDesc &, int,
+                                                 int)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, CG_STORE_POLICY);
+    }
+};
+
+// 16-bit shifted storage: q = (N / rho0_k - phi~) 2^s, N = rho0_k (phi~ + q 2^-s).
+// An absent colour (N = 0) encodes to -phi~ 2^s exactly and decodes to 0.
+template <> struct Codec<ST_F16S> {
+    using Raw = uint16_t;
+    static constexpr int bytes = 2;
+    static __device__ __forceinline__ Raw load(Rsrc r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, CG_LOAD_POLICY);
+    }
+    static __device__ __forceinline__ float dec(Raw v, const SlotDesc &S, int k, int c)
+    {
+        return S.rho0[k] * __builtin_fmaf((float)__builtin_bit_cast(_Float16, v), S.dec_mul, S.phit[k][c]);
+    }
+    static __device__ __forceinline__ void store(float v, Rsrc r, uint32_t voff, uint32_t soff, const SlotDesc &S,
+                                                 int k, int c)
+    {
+        const _Float16 q = (_Float16)__builtin_fmaf(v, S.enc_scale[k], -S.enc_off[k][c]);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, q), r, (int)voff, (int)soff, CG_STORE_POLICY);
+    }
+};
+
+template <> struct Codec<ST_BF16S> {
+    using Raw = uint16_t;
+    static constexpr int bytes = 2;
+    static __device__ __forceinline__ Raw load(Rsrc r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, CG_LOAD_POLICY);
+    }
+    static __device__ __forceinline__ float dec(Raw v, const SlotDesc &S, int k, int c)
+    {
+        const float q = __uint_as_float((uint32_t)v << 16);
+        return S.rho0[k] * __builtin_fmaf(q, S.dec_mul, S.phit[k][c]);
+    }
+    static __device__ __forceinline__ void store(float v, Rsrc r, uint32_t voff, uint32_t soff, const SlotDesc &S,
+                                                 int k, int c)
+    {
+        const float q = __builtin_fmaf(v, S.enc_scale[k], -S.enc_off[k][c]);
+        uint32_t b = __float_as_uint(q);
+        if ((b & 0x7f800000u) == 0x7f800000u) b = b | ((b & 0xffffu) ? 0x400000u : 0u);   // keep NaN a NaN
+        else b += 0x7fffu + ((b >> 16) & 1u);                                             // round to nearest even
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(b >> 16), r, (int)voff, (int)soff, CG_STORE_POLICY);
+    }
+};
+
+// The two colour halves (9 planes each) of one population buffer.
+struct Halves {
+    Rsrc r[2];
+};
+
+template <int ST>
+__device__ __forceinline__ Halves halves(const SlotDesc &S, const void *buf)
+{
+    const uint32_t half = (uint32_t)(9ll * S.plane * Codec<ST>::bytes);
+    const char *b = reinterpret_cast<const char *>(buf);
+    return Halves{{make_rsrc(b, half), make_rsrc(b + half, half)}};
+}
+
+// ------------------------------------------------------------ node state --
+struct Node {
+    float n[9];   // colour-blind streamed populations
+    float rr, rb; // colour densities (after boundary completion), correctly rounded
+    float dm;     // exact colour mass minus (rr + rb): the rounding of the FP32 densities
+    double mr, mb; // exact mass of each colour at the node (what the step must conserve)
+};
+
+// Byte offsets of the source columns of one lane for c_x = -1, 0, +1 (i.e.
+// columns x+1, x, x-1), with periodic wrap or, at an open face, a clamp (the
+// value read there is a placeholder that the Zou-He completion overwrites).
+struct XCols {
+    uint32_t off[3];
+    int x;          // the lane's own column (in range)
+    bool inlet, outlet;
+};
+
+__device__ __forceinline__ int wrapi(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <int ST>
+__device__ __forceinline__ XCols make_cols(const SlotDesc &S, int x)
+{
+    XCols c;
+    c.x = x;
+    const bool per = S.flags & F_XPER;
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {       // d = c_x of the direction
+        int sx = x - d;
+        if (per) sx = wrapi(sx, S.nx);
+        else sx = sx < 0 ? 0 : (sx >= S.nx ? S.nx - 1 : sx);
+        c.off[d + 1] = (uint32_t)sx * Codec<ST>::bytes;
+    }
+    const bool open = S.flags & F_XOPEN;
+    c.inlet = open && x == 0;
+    c.outlet = open && x == S.nx - 1;
+    return c;
+}
+
+// One real row: scalar byte offsets of the source rows for c_y = -1, 0, +1
+// and whether that neighbour row lies beyond a wall (then: bounce-back from
+// the node's own opposite population).
+struct RowSrc {
+    uint32_t off[3];
+    bool wall[3];
+    int y;
+};
+
+template <int ST>
+__device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y)
+{
+    RowSrc r;
+    r.y = y;
+    const bool per = S.flags & F_YPER;
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {       // d = c_y
+        int sy = y - d;
+        const bool out = sy < 0 || sy >= S.ny;
+        if (out && per) sy = wrapi(sy, S.ny);
+        r.wall[d + 1] = out && !per;
+        r.off[d + 1] = (uint32_t)((out && !per) ? y : sy) * (uint32_t)S.pitch * Codec<ST>::bytes;
+    }
+    return r;
+}
+
+// Raw (undecoded) populations of one node: issued first, consumed later, so
+// the loads of a row are in flight while the previous row collides.
+template <int ST> struct Raw18 {
+    typename Codec<ST>::Raw v[18];
+};
+
+template <int ST>
+__device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, const XCols &xc, const RowSrc &rw)
+{
+    using C = Codec<ST>;
+    Raw18<ST> raw;
+    const uint32_t pb = (uint32_t)S.plane * C::bytes;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int dy = cy(i) + 1;
+            // bounce-back: the node's own opposite population (same row and column)
+            const uint32_t soff = rw.wall[dy] ? (uint32_t)opp(i) * pb + rw.off[1] : (uint32_t)i * pb + rw.off[dy];
+            const uint32_t voff = rw.wall[dy] ? xc.off[1] : xc.off[cx(i) + 1];
+            raw.v[k * 9 + i] = C::load(h.r[k], voff, soff);
+        }
+    return raw;
+}
+
+// Pull gather of one node (Sec. 2 eq. (subop4)), periodic wrap and link
+// bounce-back (Sec. 2.5 items 1-2), then the two-phase Zou-He completion of
+// open columns (Sec. 2.5 item 3): west velocity inlet with the prescribed
+// colour, east pressure outlet with the colour of the six populations that
+// stream in from the domain and rho_k = chi_k p_out / c_s,k^2.
+template <int ST>
+__device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, const XCols &xc, const RowSrc &rw)
+{
+    using C = Codec<ST>;
+    Node nd;
+    double rho[2];   // colour masses, exact (nine FP32 values sum exactly in FP64)
+    float kn[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        rho[k] = 0.0;
+        kn[k] = 0.f;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const float v = C::dec(raw.v[k * 9 + i], S, k, vclass(i));
+            nd.n[i] = (k == 0) ? v : nd.n[i] + v;
+            rho[k] += (double)v;
+            if (cx(i) >= 0) kn[k] += v;   // the six populations that come from x-1 or x
+        }
+    }
+    nd.rr = (float)rho[0];
+    nd.rb = (float)rho[1];
+    if (xc.inlet) {
+        const bool red = ((const __attribute__((address_space(1))) int8_t *)S.inlet_color)[rw.y] > 0;
+        const float vx = red ? S.u_in[0] : S.u_in[1];
+        float *N = nd.n;
+        const float rin = (N[0] + N[2] + N[4] + 2.f * (N[3] + N[6] + N[7])) / (1.f - vx);
+        N[1] = N[3] + (2.f / 3.f) * rin * vx;
+        N[5] = N[7] - 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f);
+        N[8] = N[6] + 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f);
+        nd.rr = red ? rin : 0.f;
+        nd.rb = red ? 0.f : rin;
+    } else if (xc.outlet) {
+        const float vr = kn[0] * S.inv_rho0[0], vb = kn[1] * S.inv_rho0[1];
+        const float chir = vr / (vr + vb), chib = vb / (vr + vb);
+        nd.rr = chir * S.rho_out[0];
+        nd.rb = chib * S.rho_out[1];
+        const float rho_o = nd.rr + nd.rb;
+        float *N = nd.n;
+        const float vx = (N[0] + N[2] + N[4] + 2.f * (N[1] + N[5] + N[8])) / rho_o - 1.f;
+        N[3] = N[1] - (2.f / 3.f) * rho_o * vx;
+        N[6] = N[8] - 0.5f * (N[2] - N[4]) - rho_o * vx * (1.f / 6.f);
+        N[7] = N[5] + 0.5f * (N[2] - N[4]) - rho_o * vx * (1.f / 6.f);
+    }
+    if (xc.inlet || xc.outlet) {          // an open boundary prescribes the colour densities
+        rho[0] = (double)nd.rr;
+        rho[1] = (double)nd.rb;
+    }
+    // The collision relaxes towards an equilibrium of density rr + rb; the
+    // residual of their FP32 rounding, identical at every node of a uniform
+    // region, would otherwise add or remove mass coherently at every step.
+    nd.mr = rho[0];
+    nd.mb = rho[1];
+    nd.dm = (float)(rho[0] + rho[1] - (double)nd.rr - (double)nd.rb);
+    return nd;
+}
+
+// Exact colour-mass bookkeeping of the FP32 path: the rounding of the 18
+// outputs of a node (of the order of an ulp of the rest population, and the
+// same at every node of a uniform region) is measured in FP64 and returned to
+// the four diagonal populations of each colour, whose ulp is 16-32 times
+// finer.  Per step, each node then conserves the mass of each colour to a few
+// ulps of its smallest populations.
+__device__ __forceinline__ void conserve(const Node &nd, float *outr, float *outb)
+{
+    double sr = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        sr += (double)outr[i];
+        sb += (double)outb[i];
+    }
+    const float qr = (float)((nd.mr - sr) * 0.25), qb = (float)((nd.mb - sb) * 0.25);
+#pragma unroll
+    for (int i = 5; i < 9; ++i) {
+        outr[i] += qr;
+        outb[i] += qb;
+    }
+}
+
+// Store the 18 post-recolouring populations of one node.
+template <int ST>
+__device__ __forceinline__ void store18(const SlotDesc &S, const Halves &h, uint32_t voff, uint32_t rowoff,
+                                        const float *outr, const float *outb)
+{
+    using C = Codec<ST>;
+    const uint32_t pb = (uint32_t)S.plane * C::bytes;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        C::store(outr[i], h.r[0], voff, (uint32_t)i * pb + rowoff, S, 0, vclass(i));
+        C::store(outb[i], h.r[1], voff, (uint32_t)i * pb + rowoff, S, 1, vclass(i));
+    }
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// reciprocal refined by one Newton step (close to correctly rounded)
+__device__ __forceinline__ float refined_rcp(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.f), r);
+}
+
+// Colour field, Sec. 2.1.1 eq. (color_field): +1 in pure red.
+__device__ __forceinline__ float color_field(const SlotDesc &S, float rr, float rb)
+{
+    const float a = rr * S.inv_rho0[0], b = rb * S.inv_rho0[1];
+    const float psi = (a - b) * fast_rcp(a + b);
+    return b == 0.f ? 1.f : (a == 0.f ? -1.f : psi);   // exactly +-1 in a pure fluid
+}
+
+// Velocity with the half-force shift of Guo forcing.
+__device__ __forceinline__ void velocity(const SlotDesc &S, const Node &nd, float rho, float &ux, float &uy)
+{
+    const float *N = nd.n;
+    const float jx = (N[1] - N[3]) + (N[5] - N[7]) + (N[8] - N[6]);
+    const float jy = (N[2] - N[4]) + (N[5] - N[7]) + (N[6] - N[8]);
+    const float ir = fast_rcp(rho);
+    if (S.flags & F_FORCE) {
+        ux = (jx + 0.5f * rho * S.gx) * ir;
+        uy = (jy + 0.5f * rho * S.gy) * ir;
+    } else {
+        ux = jx * ir;
+        uy = jy * ir;
+    }
+}
+
+// omega_eff, quadratic interpolation across the interface (Sec. 2.1.1).
+__device__ __forceinline__ float omega_eff(const SlotDesc &S, float psi)
+{
+    if (psi > S.delta) return S.omega_r;
+    if (psi > 0.f) return S.chi + psi * (S.eta + S.kappa * psi);
+    if (psi >= -S.delta) return S.chi + psi * (S.lam + S.nu * psi);
+    return S.omega_b;
+}
+
+// M x for the D2Q9 moment basis of Appendix B (rows: rho, e, eps, jx, qx,
+// jy, qy, pxx, pxy).
+__device__ __forceinline__ void mrt_fwd(const float *f, float *m)
+{
+    const float a = f[1] + f[2] + f[3] + f[4];
+    const float d = f[5] + f[6] + f[7] + f[8];
+    m[0] = f[0] + a + d;
+    m[1] = -4.f * f[0] - a + 2.f * d;
+    m[2] = 4.f * f[0] - 2.f * a + d;
+    const float dx = f[5] - f[6] - f[7] + f[8];
+    const float dy = f[5] + f[6] - f[7] - f[8];
+    m[3] = (f[1] - f[3]) + dx;
+    m[4] = -2.f * (f[1] - f[3]) + dx;
+    m[5] = (f[2] - f[4]) + dy;
+    m[6] = -2.f * (f[2] - f[4]) + dy;
+    m[7] = (f[1] + f[3]) - (f[2] + f[4]);
+    m[8] = (f[5] + f[7]) - (f[6] + f[8]);
+}
+
+// M^{-1} m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m
+__device__ __forceinline__ void mrt_inv(const float *m, float *f)
+{
+    const float a0 = m[0] * (1.f / 9.f), a1 = m[1] * (1.f / 36.f), a2 = m[2] * (1.f / 36.f);
+    const float a3 = m[3] * (1.f / 6.f), a4 = m[4] * (1.f / 12.f), a5 = m[5] * (1.f / 6.f);
+    const float a6 = m[6] * (1.f / 12.f), a7 = m[7] * 0.25f, a8 = m[8] * 0.25f;
+    f[0] = a0 - 4.f * a1 + 4.f * a2;
+    const float ax = a0 - a1 - 2.f * a2;
+    f[1] = ax + a3 - 2.f * a4 + a7;
+    f[3] = ax - a3 + 2.f * a4 + a7;
+    f[2] = ax + a5 - 2.f * a6 - a7;
+    f[4] = ax - a5 + 2.f * a6 - a7;
+    const float dg = a0 + 2.f * a1 + a2;
+    const float px = a3 + a4, py = a5 + a6;
+    f[5] = dg + px + py + a8;
+    f[6] = dg - px + py - a8;
+    f[7] = dg - px - py + a8;
+    f[8] = dg + px - py - a8;
+}
+
+// Collision (Sec. 2.1.1 BGK / Sec. 2.1.2 MRT, colour-blind), perturbation
+// (Sec. 2.2) and recolouring (Sec. 2.3) of one node.  F = colour gradient,
+// psi = own colour field.  Output: red and blue post-recolouring populations.
+__device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float psi, float Fx, float Fy,
+                                        float *outr, float *outb)
+{
+    const float rr = nd.rr, rb = nd.rb;
+    const float rho = rr + rb;
+    float ux, uy;
+    velocity(S, nd, rho, ux, uy);
+    const float w = omega_eff(S, psi);
+    const float uu = ux * ux + uy * uy;
+
+    float neq[9];     // N - N^(e)
+    float G[9];       // Guo forcing source (force density rho g)
+    const bool force = S.flags & F_FORCE;
+    const float gxr = rho * S.gx, gyr = rho * S.gy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float cu = cx(i) * ux + cy(i) * uy;
+        const int c = vclass(i);
+        // N - N^(e) with the rest part subtracted by fused multiply-adds: the
+        // large rest populations of a heavy fluid never get rounded on their own
+        float t = __builtin_fmaf(-rr, S.phi[0][c], nd.n[i]);
+        t = __builtin_fmaf(-rb, S.phi[1][c], t);
+        // unit mass of the FP32 rest weights, and the exact mass of the node
+        if (i == 0) t -= rr * S.phi0_eps[0] + rb * S.phi0_eps[1] + nd.dm;
+        neq[i] = t - rho * wgt(i) * (3.f * cu + 4.5f * cu * cu - 1.5f * uu);
+        G[i] = force ? wgt(i) * ((3.f * (cx(i) - ux) + 9.f * cu * cx(i)) * gxr +
+                                 (3.f * (cy(i) - uy) + 9.f * cu * cy(i)) * gyr)
+                     : 0.f;
+    }
+    float ns[9];
+    if (S.flags & F_MRT) {
+        float m[9], mg[9], q[9];
+        mrt_fwd(neq, m);
+        if (force) mrt_fwd(G, mg);
+        const float sl = S.mrt_lambda * w;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const float s = (j >= 7) ? w : sl;
+            q[j] = s * m[j] - (force ? (1.f - 0.5f * s) * mg[j] : 0.f);
+        }
+        float dn[9];
+        mrt_inv(q, dn);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ns[i] = nd.n[i] - dn[i];
+    } else {
+        const float hf = 1.f - 0.5f * w;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ns[i] = __builtin_fmaf(hf, G[i], __builtin_fmaf(-w, neq[i], nd.n[i]));
+    }
+
+    const float F2 = Fx * Fx + Fy * Fy;
+    // Recolouring split: the minority colour is computed from its own fraction
+    // (keeping its relative precision in the tails of an interface) and the
+    // majority colour as the difference, so that N^r + N^b = N** holds to the
+    // last bit and the colour-blind mass is untouched by the split.
+    const float irho = refined_rcp(rho);
+    const bool red_minor = rr < rb;
+    const float cmin = (red_minor ? rr : rb) * irho;    // 0 exactly for an absent colour
+    const float cmaj = (red_minor ? rb : rr) * irho;
+    const float sgn = red_minor ? 1.f : -1.f;           // the segregation term adds to red
+    if (F2 > 1e-24f) {
+        const float inv = __builtin_amdgcn_rsqf(F2);    // 1/|F|
+        const float Fm = F2 * inv;                       // |F|
+        const float A = (S.flags & F_SIGMA) ? S.sigma94 * w : S.A;
+        const float seg = S.beta * cmin * cmaj;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const float fc = cx(i) * Fx + cy(i) * Fy;
+            const float nss = ns[i] + A * (wgt(i) * fc * fc * inv - bco(i) * Fm);
+            float sg = 0.f;
+            if (i != 0) {
+                const int c = vclass(i);
+                const float cosphi = fc * inv * (c == 1 ? 1.f : 0.70710678118654752f);
+                sg = seg * cosphi * (rr * S.phi[0][c] + rb * S.phi[1][c]);
+            }
+            const float mino = cmin * nss + sgn * sg;
+            const float majo = nss - mino;
+            outr[i] = red_minor ? mino : majo;
+            outb[i] = red_minor ? majo : mino;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const float mino = cmin * ns[i];
+            const float majo = ns[i] - mino;
+            outr[i] = red_minor ? mino : majo;
+            outb[i] = red_minor ? majo : mino;
+        }
+    }
+}
+
+}  // namespace cgd

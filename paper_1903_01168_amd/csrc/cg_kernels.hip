@@ -1,0 +1,414 @@
+// cg_kernels.hip -- HIP kernels of the colour-gradient D2Q9 step for gfx950.
+//
+//  k_step      one fused time step over a set of lattices ("slots"): pull
+//              gather + boundary completion, colour field, S2I4 gradient,
+//              omega_eff, BGK/MRT, perturbation, recolouring, store.  Every
+//              wavefront owns 60 columns (plus 2 overlap columns on each side)
+//              of a strip of rows and marches up the strip on its own.
+//  k_init      equilibrium initialisation from FP32 fields.
+//  k_moments   fields at the current step (+ FP64 per-block diagnostics).
+//  k_reduce    fixed-order FP64 reduction of the per-block partials.
+//  k_get/set   decode / encode the stored populations to a plain FP32 layout.
+//  k_copy      plain streaming copy (achievable-bandwidth reference).
+#include "cg_kernels.hpp"
+
+namespace cgd {
+
+// Tiles are dealt to the 8 XCDs round-robin by workgroup id; remap so that
+// every XCD receives one contiguous range of logical tiles (neighbouring strips
+// of one column share halo rows through that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int b, int total)
+{
+    const int q = total >> 3, r = total & 7;
+    const int x = b & 7, j = b >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
+__device__ __forceinline__ int find_slot(const SlotDesc *__restrict__ slots, int nslots, int tile)
+{
+    int lo = 0, hi = nslots - 1;
+    while (lo < hi) {             // last slot with tile_begin <= tile
+        const int mid = (lo + hi + 1) >> 1;
+        if (slots[mid].tile_begin <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Cross-lane neighbours inside a wavefront (DPP wave shifts): the value of
+// lane l-1 (west) and of lane l+1 (east).
+__device__ __forceinline__ float from_west(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_east(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// Colour field of one row with its west and east neighbours.
+struct Psi3 {
+    float w, c, e;
+};
+
+__device__ __forceinline__ Psi3 psi3(float c) { return Psi3{from_west(c), c, from_east(c)}; }
+
+// Wave tile: 64 lanes cover columns xw-2 .. xw+61 and write xw .. xw+59.
+constexpr int kOut = 60;
+
+// One fused time step.  Every wavefront owns kOut columns of a strip of rows
+// and marches up the strip on its own (no LDS, no barrier): the colour field
+// of the rows y-1, y, y+1 lives in registers, horizontal neighbours come from
+// the adjacent lanes, and the populations of row y+2 are requested before row
+// y collides.
+template <int ST, int W>
+__global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
+                                                 int parity, int launch_idx)
+{
+    const int tile = xcd_tile(blockIdx.x, total_tiles);
+    const SlotDesc S = slots[find_slot(slots, nslots, tile)];
+    if (launch_idx >= S.active_steps) return;
+
+    // tiles of a lattice run x-fastest: concurrently resident wavefronts then
+    // stream neighbouring segments of the same rows (DRAM page locality), and
+    // vertically adjacent strips land on the same XCD (shared halo rows in L2)
+    const int lt = tile - S.tile_begin;
+    const int tyi = lt / S.tiles_x;
+    const int txi = lt - tyi * S.tiles_x;
+    const int nx = S.nx, ny = S.ny;
+    const int lane = threadIdx.x & 63;
+    const int xw = (txi * W + (int)(threadIdx.x >> 6)) * kOut;
+    if (xw >= nx) return;                      // uniform per wavefront
+    const int y0 = tyi * S.strip;
+    const int y1 = min(y0 + S.strip, ny);
+    const bool yper = S.flags & F_YPER;
+    const bool xper = S.flags & F_XPER;
+
+    const int xl = xw - 2 + lane;              // the lane's column (may lie outside the lattice)
+    const int xg = xper ? wrapi(xl, nx) : (xl < 0 ? 0 : (xl >= nx ? nx - 1 : xl));
+    const bool out_lane = lane >= 2 && lane < 62 && xl < nx;
+    const XCols xc = make_cols<ST>(S, xg);
+    const Halves src = halves<ST>(S, parity ? S.buf[1] : S.buf[0]);
+    const Halves dst = halves<ST>(S, parity ? S.buf[0] : S.buf[1]);
+
+    // wall ghost row from the adjacent fluid row (Sec. 2.4 extrapolation):
+    // W-weighted mean over the fluid neighbours, axis : diagonal = 4 : 1,
+    // neighbours beyond an open x face excluded
+    const bool in0 = xper || (xl >= 0 && xl < nx);
+    const bool inw = xper || (xl - 1 >= 0 && xl - 1 < nx);
+    const bool ine = xper || (xl + 1 >= 0 && xl + 1 < nx);
+    const float gden = (in0 ? 4.f : 0.f) + (inw ? 1.f : 0.f) + (ine ? 1.f : 0.f);
+    const float ginv = gden > 0.f ? fast_rcp(gden) : 0.f;
+    auto ghost = [&](const Psi3 &f) -> Psi3 {
+        const float g = ((in0 ? 4.f * f.c : 0.f) + (inw ? f.w : 0.f) + (ine ? f.e : 0.f)) * ginv;
+        return psi3(g);
+    };
+    auto real_row = [&](int r) { return yper ? wrapi(r, ny) : r; };
+    auto gathered = [&](int r) { return yper || (r >= 0 && r < ny); };
+
+    // prologue: rows y0-1 and y0
+    Psi3 pm, p0;
+    Node cur;
+    {
+        const bool have_m = gathered(y0 - 1);
+        Raw18<ST> rm;
+        const RowSrc rwm = make_row<ST>(S, real_row(y0 - 1 >= 0 || yper ? y0 - 1 : 0));
+        if (have_m) rm = issue<ST>(S, src, xc, rwm);
+        const RowSrc rw0 = make_row<ST>(S, y0);
+        const Raw18<ST> r0 = issue<ST>(S, src, xc, rw0);
+        if (have_m) {
+            const Node t = finish<ST>(S, rm, xc, rwm);
+            pm = psi3(color_field(S, t.rr, t.rb));
+        }
+        cur = finish<ST>(S, r0, xc, rw0);
+        p0 = psi3(color_field(S, cur.rr, cur.rb));
+        if (!have_m) pm = ghost(p0);
+    }
+    bool have_p = gathered(y0 + 1);
+    RowSrc rwp = make_row<ST>(S, have_p ? real_row(y0 + 1) : y0);
+    Raw18<ST> pend;
+    if (have_p) pend = issue<ST>(S, src, xc, rwp);
+
+    const uint32_t rowbytes = (uint32_t)S.pitch * Codec<ST>::bytes;
+    for (int y = y0; y < y1; ++y) {
+        Node nxt;
+        Psi3 pp;
+        if (have_p) {
+            nxt = finish<ST>(S, pend, xc, rwp);
+            pp = psi3(color_field(S, nxt.rr, nxt.rb));
+        } else {
+            pp = ghost(p0);                    // row y+1 = ny lies beyond the top wall
+        }
+        // request row y+2 now; it arrives while row y collides
+        have_p = (y + 2 <= y1) && gathered(y + 2);
+        if (have_p) {
+            rwp = make_row<ST>(S, real_row(y + 2));
+            pend = issue<ST>(S, src, xc, rwp);
+        }
+        if (out_lane) {
+            // S2I4 gradient, Sec. 2.2 eq. (colorGradient): xi = 1/3 axis, 1/12 diagonal
+            const float Fx = (1.f / 3.f) * (p0.e - p0.w) + (1.f / 12.f) * ((pp.e - pp.w) + (pm.e - pm.w));
+            const float Fy = (1.f / 3.f) * (pp.c - pm.c) + (1.f / 12.f) * ((pp.e + pp.w) - (pm.e + pm.w));
+            float outr[9], outb[9];
+            collide(S, cur, p0.c, Fx, Fy, outr, outb);
+            if (ST == ST_F32) conserve(cur, outr, outb);   // 16-bit storage rounds far coarser
+            store18<ST>(S, dst, xc.off[1], (uint32_t)y * rowbytes, outr, outb);
+        }
+        pm = p0;
+        p0 = pp;
+        cur = nxt;
+    }
+}
+
+// ---------------------------------------------------------------- init --
+template <int ST>
+__global__ void __launch_bounds__(256) k_init(const SlotDesc *__restrict__ sd, const float *__restrict__ f,
+                                              int which)
+{
+    const SlotDesc S = *sd;
+    const long long n = (long long)S.nx * S.ny;
+    const Halves dst = halves<ST>(S, which ? S.buf[1] : S.buf[0]);
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(c / S.nx), x = (int)(c - (long long)y * S.nx);
+        const float rk[2] = {f[c], f[n + c]};
+        const float ux = f[2 * n + c], uy = f[3 * n + c];
+        const float uu = ux * ux + uy * uy;
+        float e[2][9];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const float cu = cx(i) * ux + cy(i) * uy;
+                // Sec. 2.1.1 eq. (equilibrium)
+                e[k][i] = rk[k] * (S.phi[k][vclass(i)] + wgt(i) * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+                if (i == 0) e[k][i] += rk[k] * S.phi0_eps[k];
+            }
+        store18<ST>(S, dst, (uint32_t)x * Codec<ST>::bytes, (uint32_t)y * S.pitch * Codec<ST>::bytes, e[0], e[1]);
+    }
+}
+
+// ------------------------------------------------------------- moments --
+// Per node: gather + completion, fields (optional) and FP64 partial sums.
+// Partials per block: [0] mass_r [1] mass_b [2] area_r [3] p-sum inside
+// [4] n inside [5] p-sum outside [6] n outside [7] n non-finite [8] max |u|
+template <int ST>
+__global__ void __launch_bounds__(256) k_moments(const SlotDesc *__restrict__ sd, int parity,
+                                                 float *__restrict__ fields, double *__restrict__ partial,
+                                                 double cxc, double cyc, double r_in, double r_out)
+{
+    const SlotDesc S = *sd;
+    const long long n = (long long)S.nx * S.ny;
+    const Halves src = halves<ST>(S, parity ? S.buf[1] : S.buf[0]);
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(c / S.nx), x = (int)(c - (long long)y * S.nx);
+        const XCols xc = make_cols<ST>(S, x);
+        const RowSrc rw = make_row<ST>(S, y);
+        const Node nd = finish<ST>(S, issue<ST>(S, src, xc, rw), xc, rw);
+        const float rho = nd.rr + nd.rb;
+        float ux, uy;
+        velocity(S, nd, rho, ux, uy);
+        const float p = nd.rr * S.cs2[0] + nd.rb * S.cs2[1];
+        if (fields) {
+            fields[c] = nd.rr;
+            fields[n + c] = nd.rb;
+            fields[2 * n + c] = ux;
+            fields[3 * n + c] = uy;
+            fields[4 * n + c] = p;
+        }
+        const bool finite = __builtin_isfinite(nd.rr) && __builtin_isfinite(nd.rb) && __builtin_isfinite(ux) &&
+                            __builtin_isfinite(uy);
+        if (!finite) {
+            acc[7] += 1.0;
+            continue;
+        }
+        acc[0] += (double)nd.rr;
+        acc[1] += (double)nd.rb;
+        acc[2] += 0.5 * (1.0 + (double)color_field(S, nd.rr, nd.rb));
+        const double um = sqrt((double)ux * ux + (double)uy * uy);
+        acc[8] = um > acc[8] ? um : acc[8];
+        if (r_in > 0.0 || r_out > 0.0) {
+            const double dx = x + 0.5 - cxc, dy = y + 0.5 - cyc;
+            const double r2 = dx * dx + dy * dy;
+            if (r2 < r_in * r_in) { acc[3] += p; acc[4] += 1.0; }
+            if (r2 > r_out * r_out) { acc[5] += p; acc[6] += 1.0; }
+        }
+    }
+    // wavefront reduction (64 lanes), then across the 4 waves through LDS
+    __shared__ double red[4][9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        double v = acc[j];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(v, off, 64);
+            v = (j == 8) ? (o > v ? o : v) : v + o;
+        }
+        acc[j] = v;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int j = 0; j < 9; ++j) red[wv][j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int j = threadIdx.x;
+        double v = red[0][j];
+        for (int w = 1; w < 4; ++w) v = (j == 8) ? (red[w][j] > v ? red[w][j] : v) : v + red[w][j];
+        partial[(long long)blockIdx.x * 9 + j] = v;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_reduce(const double *__restrict__ partial, int nblocks,
+                                               double *__restrict__ out)
+{
+    // one wave; lane j < 9 sums column j over the blocks in block order
+    const int j = threadIdx.x;
+    if (j >= 9) return;
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        const double p = partial[(long long)b * 9 + j];
+        v = (j == 8) ? (p > v ? p : v) : v + p;
+    }
+    out[j] = v;
+}
+
+// ---------------------------------------------------- population access --
+template <int ST>
+__global__ void __launch_bounds__(256) k_get_pops(const SlotDesc *__restrict__ sd, int which,
+                                                  float *__restrict__ out)
+{
+    using C = Codec<ST>;
+    const SlotDesc S = *sd;
+    const long long n = (long long)S.nx * S.ny;
+    const Halves src = halves<ST>(S, which ? S.buf[1] : S.buf[0]);
+    const uint32_t pb = (uint32_t)S.plane * C::bytes;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(c / S.nx), x = (int)(c - (long long)y * S.nx);
+        const uint32_t voff = (uint32_t)x * C::bytes, roff = (uint32_t)y * S.pitch * C::bytes;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                out[(long long)(k * 9 + i) * n + c] = C::dec(C::load(src.r[k], voff, (uint32_t)i * pb + roff), S, k, vclass(i));
+    }
+}
+
+template <int ST>
+__global__ void __launch_bounds__(256) k_set_pops(const SlotDesc *__restrict__ sd, int which,
+                                                  const float *__restrict__ in)
+{
+    using C = Codec<ST>;
+    const SlotDesc S = *sd;
+    const long long n = (long long)S.nx * S.ny;
+    const Halves dst = halves<ST>(S, which ? S.buf[1] : S.buf[0]);
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(c / S.nx), x = (int)(c - (long long)y * S.nx);
+        float r[9], b[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            r[i] = in[(long long)i * n + c];
+            b[i] = in[(long long)(9 + i) * n + c];
+        }
+        store18<ST>(S, dst, (uint32_t)x * C::bytes, (uint32_t)y * S.pitch * C::bytes, r, b);
+    }
+}
+
+// ------------------------------------------------------------------ copy --
+__global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, long long n16)
+{
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n16;
+         c += (long long)gridDim.x * blockDim.x)
+        dst[c] = src[c];
+}
+
+// ------------------------------------------------------------- launchers --
+template <int ST>
+static hipError_t step_st(int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx, hipStream_t s)
+{
+    switch (tx) {
+    case 64: hipLaunchKernelGGL((k_step<ST, 1>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
+    case 128: hipLaunchKernelGGL((k_step<ST, 2>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
+    case 256: hipLaunchKernelGGL((k_step<ST, 4>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int storage, int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx,
+                       hipStream_t s)
+{
+    switch (storage) {
+    case ST_F32: return step_st<ST_F32>(tx, d, nslots, tiles, parity, idx, s);
+    case ST_F16S: return step_st<ST_F16S>(tx, d, nslots, tiles, parity, idx, s);
+    case ST_BF16S: return step_st<ST_BF16S>(tx, d, nslots, tiles, parity, idx, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static int grid_for(long long n) { long long g = (n + 255) / 256; return (int)(g < 1 ? 1 : (g > 2048 ? 2048 : g)); }
+
+hipError_t launch_init(int storage, const SlotDesc *d, long long nodes, const float *fields, int which, hipStream_t s)
+{
+    const int g = grid_for(nodes);
+    switch (storage) {
+    case ST_F32: hipLaunchKernelGGL(k_init<ST_F32>, dim3(g), dim3(256), 0, s, d, fields, which); break;
+    case ST_F16S: hipLaunchKernelGGL(k_init<ST_F16S>, dim3(g), dim3(256), 0, s, d, fields, which); break;
+    case ST_BF16S: hipLaunchKernelGGL(k_init<ST_BF16S>, dim3(g), dim3(256), 0, s, d, fields, which); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int moments_blocks(long long nodes) { return grid_for(nodes); }
+
+hipError_t launch_moments(int storage, const SlotDesc *d, long long nodes, int parity, float *fields,
+                          double *partial, double *out, const double *circle, hipStream_t s)
+{
+    const int g = grid_for(nodes);
+    const double c0 = circle ? circle[0] : 0.0, c1 = circle ? circle[1] : 0.0;
+    const double ri = circle ? circle[2] : -1.0, ro = circle ? circle[3] : -1.0;
+    switch (storage) {
+    case ST_F32: hipLaunchKernelGGL(k_moments<ST_F32>, dim3(g), dim3(256), 0, s, d, parity, fields, partial, c0, c1, ri, ro); break;
+    case ST_F16S: hipLaunchKernelGGL(k_moments<ST_F16S>, dim3(g), dim3(256), 0, s, d, parity, fields, partial, c0, c1, ri, ro); break;
+    case ST_BF16S: hipLaunchKernelGGL(k_moments<ST_BF16S>, dim3(g), dim3(256), 0, s, d, parity, fields, partial, c0, c1, ri, ro); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, s, partial, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pops(int storage, const SlotDesc *d, long long nodes, int which, float *buf, bool get,
+                       hipStream_t s)
+{
+    const int g = grid_for(nodes);
+#define CG_POPS(ST)                                                                                   \
+    if (get) hipLaunchKernelGGL(k_get_pops<ST>, dim3(g), dim3(256), 0, s, d, which, buf);             \
+    else hipLaunchKernelGGL(k_set_pops<ST>, dim3(g), dim3(256), 0, s, d, which, (const float *)buf);
+    switch (storage) {
+    case ST_F32: CG_POPS(ST_F32) break;
+    case ST_F16S: CG_POPS(ST_F16S) break;
+    case ST_BF16S: CG_POPS(ST_BF16S) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef CG_POPS
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t n, hipStream_t s)
+{
+    const long long n16 = (long long)(n / 16);
+    if (n16 > 0) {
+        long long g = (n16 + 255) / 256;
+        if (g > 8192) g = 8192;
+        hipLaunchKernelGGL(k_copy, dim3((int)g), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cgd

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI: the library loads, exports every function the
+header declares, and validates parameters (no GPU calls)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1903_01168_amd import build as B
+from paper_1903_01168_amd import capi
+from paper_1903_01168_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if B.is_stale():
+        B.build()
+    return capi.load()
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_\w+)\s*\(", text)))
+
+
+def test_exports_match_header(lib):
+    declared = _declared("cglbm.h")
+    out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (lbm_\w+)$", out, flags=re.M))
+    missing = [d for d in declared if d not in exported]
+    assert not missing, missing
+    for name in declared:
+        assert hasattr(lib, name)
+    assert sorted(capi.EXPORTS) == [d for d in declared if d in capi.EXPORTS]
+    assert set(capi.EXPORTS) <= set(declared)
+
+
+def test_version(lib):
+    assert capi.version().startswith("cglbm")
+
+
+def _bytes(p):
+    return capi.load().lbm_bytes_required(C.byref(capi.make_params(p)))
+
+
+def test_layout_sizes(lib):
+    p = W.params(nx=100, ny=10)
+    cp = capi.make_params(p)
+    # 18 planes, pitch padded to 64
+    assert lib.lbm_buffer_bytes(C.byref(cp)) == 18 * 128 * 10 * 4
+    p16 = W.params(nx=100, ny=10, storage="f16s")
+    assert lib.lbm_buffer_bytes(C.byref(capi.make_params(p16))) == 18 * 128 * 10 * 2
+    assert _bytes(p) > 2 * 18 * 128 * 10 * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(tau_r=0.5), dict(tau_b=0.4), dict(beta=1.5), dict(rho0_r=0.0),
+    dict(A=1e-3, sigma=1e-3), dict(alpha_light=1.0), dict(delta=0.0),
+    dict(bc_x="open", p_out=0.0), dict(bc_x="open", nx=1, p_out=0.48),
+    dict(bc_x="open", p_out=0.48, u_in_r=1.5),
+])
+def test_validation_rejects(lib, bad):
+    kw = dict(nx=16, ny=8, A=1e-3)
+    kw.update(bad)
+    assert _bytes(W.params(**kw)) == 0
+
+
+def test_validation_accepts(lib):
+    for kw in (dict(), dict(bc_x="open", p_out=0.48), dict(bc_y="walls", gx=1e-6),
+               dict(collision="mrt"), dict(storage="bf16s"), dict(A=0.0, sigma=1e-3)):
+        base = dict(nx=16, ny=8, A=1e-3)
+        base.update(kw)
+        assert _bytes(W.params(**base)) > 0
+
+
+def test_unpaired_faces_rejected(lib):
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3))
+    cp.bc_xhi = capi.BC["zouhe_pressure"]
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3))
+    cp.bc_ylo = capi.BC["bounceback"]
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3))
+    cp.bc_ylo = cp.bc_yhi = capi.BC["zouhe_velocity"]
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
