@@ -204,7 +204,10 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
     d.flags = f;
 }
 
-int default_tx(int nx) { return nx >= 256 ? 256 : (nx >= 128 ? 128 : 64); }
+// One wavefront per workgroup suits lattices up to a few million nodes (finer
+// load balance); four wavefronts side by side stream longer row segments,
+// which pays on HBM-resident lattices.
+int default_tx(int nx, int ny) { return (long long)nx * ny >= (1LL << 23) ? 256 : 64; }
 
 // A wavefront writes 60 columns (it reads 2 more on each side).
 static const int kWaveCols = 60;
@@ -215,13 +218,10 @@ int plan_strip(int nx, int ny, int tx, int req)
 {
     (void)tx;
     if (req > 0) return req < ny ? req : ny;
-    const long long waves_per_row = wave_tiles(nx);
-    // aim at ~16K waves in flight (64 per CU), strips of 4..64 rows
-    long long strip = (waves_per_row * ny + 16383) / 16384;
-    if (strip < 4) strip = 4;
-    if (strip > 64) strip = 64;
-    if (strip > ny) strip = ny;
-    return (int)strip;
+    (void)nx;
+    // strips of 8 rows: 25% of the gathers are halo rows (served by L2) but the
+    // chip gets enough independent wavefronts; measured best from 512^2 to 8192^2
+    return ny < 8 ? ny : 8;
 }
 
 void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip)
@@ -258,7 +258,7 @@ static void drop_graphs(lbm_ctx *c)
 
 static int replan(lbm_ctx *c)
 {
-    const int tx = c->tx ? c->tx : default_tx(c->p.nx);
+    const int tx = c->tx ? c->tx : default_tx(c->p.nx, c->p.ny);
     const int strip = plan_strip(c->p.nx, c->p.ny, tx, c->strip_req);
     set_geometry(c->desc, &c->p, c->lay, tx, strip);
     c->desc.tile_begin = 0;
@@ -714,7 +714,7 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
     int tx = tile_x;
     if (!tx) {
         tx = 256;
-        for (int i = 0; i < n; ++i) tx = std::min(tx, default_tx(ctxs[i]->p.nx));
+        for (int i = 0; i < n; ++i) tx = std::min(tx, default_tx(ctxs[i]->p.nx, ctxs[i]->p.ny));
     }
     b->tx = tx;
     long long tiles = 0;

@@ -23,7 +23,7 @@ int fail(lbm_ctx *c, int code, const std::string &msg);
 int validate(const lbm_params *p, std::string &msg);
 Layout layout(const lbm_params *p);
 void fill_desc(const lbm_params *p, cgd::SlotDesc &d);
-int default_tx(int nx);
+int default_tx(int nx, int ny);
 int plan_strip(int nx, int ny, int tx, int req);
 void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip);
 

@@ -106,56 +106,66 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
     auto real_row = [&](int r) { return yper ? wrapi(r, ny) : r; };
     auto gathered = [&](int r) { return yper || (r >= 0 && r < ny); };
 
-    // prologue: rows y0-1 and y0
-    Psi3 pm, p0;
+    // Even strips march up, odd strips march down: the two strips on either
+    // side of a strip boundary then read their shared halo rows at the same
+    // time (both at the start or both at the end), so the second read hits L2.
+    const int d = (tyi & 1) ? -1 : 1;
+    const int ys = d > 0 ? y0 : y1 - 1;       // first row written
+    const int ye = d > 0 ? y1 : y0 - 1;       // one past the last row written
+
+    // prologue: the row behind the first one, and the first one
+    Psi3 pb, p0;                               // colour field of rows y-d and y
     Node cur;
     {
-        const bool have_m = gathered(y0 - 1);
-        Raw18<ST> rm;
-        const RowSrc rwm = make_row<ST>(S, real_row(y0 - 1 >= 0 || yper ? y0 - 1 : 0));
-        if (have_m) rm = issue<ST>(S, src, xc, rwm);
-        const RowSrc rw0 = make_row<ST>(S, y0);
+        const bool have_b = gathered(ys - d);
+        Raw18<ST> rb;
+        const RowSrc rwb = make_row<ST>(S, have_b ? real_row(ys - d) : ys);
+        if (have_b) rb = issue<ST>(S, src, xc, rwb);
+        const RowSrc rw0 = make_row<ST>(S, ys);
         const Raw18<ST> r0 = issue<ST>(S, src, xc, rw0);
-        if (have_m) {
-            const Node t = finish<ST>(S, rm, xc, rwm);
-            pm = psi3(color_field(S, t.rr, t.rb));
+        if (have_b) {
+            const Node t = finish<ST>(S, rb, xc, rwb);
+            pb = psi3(color_field(S, t.rr, t.rb));
         }
         cur = finish<ST>(S, r0, xc, rw0);
         p0 = psi3(color_field(S, cur.rr, cur.rb));
-        if (!have_m) pm = ghost(p0);
+        if (!have_b) pb = ghost(p0);           // the row behind lies beyond a wall
     }
-    bool have_p = gathered(y0 + 1);
-    RowSrc rwp = make_row<ST>(S, have_p ? real_row(y0 + 1) : y0);
+    bool have_p = gathered(ys + d);
+    RowSrc rwp = make_row<ST>(S, have_p ? real_row(ys + d) : ys);
     Raw18<ST> pend;
     if (have_p) pend = issue<ST>(S, src, xc, rwp);
 
     const uint32_t rowbytes = (uint32_t)S.pitch * Codec<ST>::bytes;
-    for (int y = y0; y < y1; ++y) {
+    const float fd = (float)d;
+    for (int y = ys; y != ye; y += d) {
         Node nxt;
-        Psi3 pp;
+        Psi3 pa;                               // colour field of row y+d (ahead)
         if (have_p) {
             nxt = finish<ST>(S, pend, xc, rwp);
-            pp = psi3(color_field(S, nxt.rr, nxt.rb));
+            pa = psi3(color_field(S, nxt.rr, nxt.rb));
         } else {
-            pp = ghost(p0);                    // row y+1 = ny lies beyond the top wall
+            pa = ghost(p0);                    // row y+d lies beyond a wall
         }
-        // request row y+2 now; it arrives while row y collides
-        have_p = (y + 2 <= y1) && gathered(y + 2);
+        // request row y+2d now; it arrives while row y collides
+        const int r2 = y + 2 * d;
+        have_p = (d > 0 ? r2 <= y1 : r2 >= y0 - 1) && gathered(r2);
         if (have_p) {
-            rwp = make_row<ST>(S, real_row(y + 2));
+            rwp = make_row<ST>(S, real_row(r2));
             pend = issue<ST>(S, src, xc, rwp);
         }
         if (out_lane) {
-            // S2I4 gradient, Sec. 2.2 eq. (colorGradient): xi = 1/3 axis, 1/12 diagonal
-            const float Fx = (1.f / 3.f) * (p0.e - p0.w) + (1.f / 12.f) * ((pp.e - pp.w) + (pm.e - pm.w));
-            const float Fy = (1.f / 3.f) * (pp.c - pm.c) + (1.f / 12.f) * ((pp.e + pp.w) - (pm.e + pm.w));
+            // S2I4 gradient, Sec. 2.2 eq. (colorGradient): xi = 1/3 axis, 1/12 diagonal;
+            // rows y+1 / y-1 are ahead / behind when marching up, the reverse when down
+            const float Fx = (1.f / 3.f) * (p0.e - p0.w) + (1.f / 12.f) * ((pa.e - pa.w) + (pb.e - pb.w));
+            const float Fy = fd * ((1.f / 3.f) * (pa.c - pb.c) + (1.f / 12.f) * ((pa.e + pa.w) - (pb.e + pb.w)));
             float outr[9], outb[9];
             collide(S, cur, p0.c, Fx, Fy, outr, outb);
             if (ST == ST_F32) conserve(cur, outr, outb);   // 16-bit storage rounds far coarser
             store18<ST>(S, dst, xc.off[1], (uint32_t)y * rowbytes, outr, outb);
         }
-        pm = p0;
-        p0 = pp;
+        pb = p0;
+        p0 = pa;
         cur = nxt;
     }
 }
