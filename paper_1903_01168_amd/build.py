@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcglbm.so")
-SOURCES = ["cg_kernels.hip", "cg_capi.cpp"]
+SOURCES = ["cg_kernels.hip", "cg_capi.cpp", "cg_server.cpp"]
 HEADERS = ["cg_device.hpp", "cg_kernels.hpp", "cg_capi_internal.hpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions (v_pk_*_f32) in device code.
@@ -26,7 +26,7 @@ def sources():
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = ["hipcc", *FLAGS, *extra, "-o", LIB + ".tmp", *sources()]
+    cmd = ["hipcc", *FLAGS, *extra, "-o", LIB + ".tmp", *sources(), "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -38,7 +38,8 @@ def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    deps = sources() + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", "cglbm.h")]
+    deps = sources() + [os.path.join(CSRC, h) for h in HEADERS] + \
+        [os.path.join(ROOT, "include", h) for h in ("cglbm.h", "cglbm_serve.h")]
     return any(os.path.exists(d) and os.path.getmtime(d) > t for d in deps)
 
 

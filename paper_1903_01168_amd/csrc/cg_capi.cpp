@@ -38,28 +38,6 @@ struct DeviceGuard {
 
 }  // namespace
 
-struct lbm_ctx {
-    lbm_params p{};
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
-    void *buf[2] = {nullptr, nullptr};
-    bool own_buf = false;
-    size_t buf_bytes = 0;
-    cgi::Layout lay{};
-    int8_t *d_inlet = nullptr;
-    SlotDesc desc{};
-    SlotDesc *d_desc = nullptr;
-    float *d_fields = nullptr;          // 5 n floats: init input / moments output
-    double *d_partial = nullptr;
-    double *d_out = nullptr;
-    int64_t steps = 0;
-    int tx = 0, strip_req = 0, tiles = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    int graph_len = 0;
-    std::string err;
-};
 
 namespace cgi {
 

@@ -3,12 +3,13 @@
 // launch planning.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
 #include <string>
 
 #include "cg_device.hpp"
 #include "cglbm.h"
-
-struct lbm_ctx;
 
 namespace cgi {
 
@@ -18,6 +19,34 @@ struct Layout {
     long long plane = 0;     // elements per plane
     size_t buf_bytes = 0;    // one buffer: 18 planes
 };
+
+}  // namespace cgi
+
+// One lattice on one device (the object behind the opaque lbm_ctx handle).
+struct lbm_ctx {
+    lbm_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+    void *buf[2] = {nullptr, nullptr};
+    bool own_buf = false;
+    size_t buf_bytes = 0;
+    cgi::Layout lay{};
+    int8_t *d_inlet = nullptr;
+    cgd::SlotDesc desc{};
+    cgd::SlotDesc *d_desc = nullptr;
+    float *d_fields = nullptr;          // 5 n floats: init input / moments output
+    double *d_partial = nullptr;
+    double *d_out = nullptr;
+    int64_t steps = 0;
+    int tx = 0, strip_req = 0, tiles = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_len = 0;
+    std::string err;
+};
+
+namespace cgi {
 
 int fail(lbm_ctx *c, int code, const std::string &msg);
 int validate(const lbm_params *p, std::string &msg);
