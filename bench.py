@@ -10,7 +10,8 @@ resident in HBM before the timed region starts.
 
 Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
 (algorithmic bytes 144 B per lattice update in FP32 -- 18 populations read and
-written -- or 72 B with 16-bit storage, against 8 TB/s), the FP64 CPU oracle
+written -- or 80 B with 16-bit storage, where the 16 moving populations take
+2 B and the two rest populations 4 B, against 8 TB/s), the FP64 CPU oracle
 timed on a bounded sample on the host cores, and per-lattice diagnostics.
 """
 import argparse
@@ -39,7 +40,7 @@ def kernel_hash():
 
 
 def bytes_per_update(storage):
-    return 144 if storage == "f32" else 72
+    return 144 if storage == "f32" else 80
 
 
 def build_cells(args, W):
@@ -96,19 +97,259 @@ def cpu_baseline(cell, seconds):
                        f"{dt:.1f} s")
 
 
+def precision_report(sid, steps=20000):
+    """Converged 64 x 64 static bubble (R = 16, A = 1e-3, beta = 0.7): the
+    pressure jump and colour-mass drift of each storage format against the FP64
+    oracle (run on the host cores here)."""
+    import numpy as np
+    import oracle
+    from paper_1903_01168_amd import capi
+    from paper_1903_01168_amd import workloads as W
+    c = W.static_bubble(n=64, radius=16)
+    p = c["params"]
+    s = oracle.Sim(**p).init(c["rho_r"], c["rho_b"], None, None)
+    s.step(steps)
+    m = s.moments()
+    a, b = m["rho_r"] / p["rho0_r"], m["rho_b"] / p["rho0_b"]
+    R = math.sqrt((0.5 * (1 + (a - b) / (a + b))).sum() / math.pi)
+    y, x = np.mgrid[0:64, 0:64]
+    r = np.hypot(x + 0.5 - 32, y + 0.5 - 32)
+    dp64 = float(m["p"][r < R - 4].mean() - m["p"][r > R + 4].mean())
+    sigma = 4.0 * p["A"] / 9.0
+    out = {"case": f"static bubble 64x64 R=16, {steps} steps", "fp64_dp": dp64,
+           "fp64_laplace_err": abs(dp64 / (sigma / R) - 1.0)}
+    m0 = (c["rho_r"].sum(), c["rho_b"].sum())
+    for st in ("f32", "f16s", "bf16s"):
+        with capi.Lattice(dict(p, storage=st), stream=sid) as g:
+            g.init(c["rho_r"], c["rho_b"])
+            g.step(steps)
+            d = g.diag(check=False)
+            Rg = math.sqrt(d["area_r"] / math.pi)
+            d = g.diag(circle=(32.0, 32.0, Rg - 4, Rg + 4), check=False)
+        dp = d["p_in"] - d["p_out"]
+        out[st] = {"dp_rel_to_fp64": dp / dp64 - 1.0, "laplace_err": abs(dp / (sigma / Rg) - 1.0),
+                   "mass_drift_r": d["mass_r"] / m0[0] - 1.0, "mass_drift_b": d["mass_b"] / m0[1] - 1.0,
+                   "max_u": d["max_u"]}
+    return out
+
+
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
+
+
+def serve_init(geo):
+    from paper_1903_01168_amd import serve
+    if geo["kind"] == "disk":
+        return serve.init_disk(geo["cx"], geo["cy"], geo["radius"], geo["rho_r_in"], geo["rho_b_in"],
+                               geo["rho_r_out"], geo["rho_b_out"])
+    return serve.init_bands(geo["edges"], geo["rho_band_r"], geo["rho_band_b"])
+
+
+def dp_of(diag, req):
+    """Laplace pressure jump of a bubble request and its theoretical value."""
+    if req["kind"] != "bubble" or diag["n_nonfinite"] > 0 or diag["n_in"] == 0 or diag["n_out"] == 0:
+        return None
+    R = math.sqrt(diag["area_r"] / math.pi)
+    return diag["p_in"] - diag["p_out"], req["params"]["sigma"] / R
+
+
+def run_serve(args, log):
+    """Serving mix: Poisson arrivals of bubble and slug solves of mixed sizes,
+    served by the continuous-batching server in 16-bit shifted storage, then
+    the same trace solved one at a time on the plain FP32 single-lattice path
+    (FIFO; the queueing of that baseline is replayed from measured solve
+    times against the same arrival times)."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_1903_01168_amd import capi, serve
+    from paper_1903_01168_amd import workloads as W
+
+    capi.load()
+    torch.cuda.init()
+    trace = W.serve_trace(seed=args.seed, n=args.requests, storage=args.storage)
+    lu = np.array([r["nodes"] * r["steps"] for r in trace], dtype=np.float64)
+    budget = int(args.hbm_budget_gib * (1 << 30))
+
+    # capacity at moderate concurrency: a closed batch of the first requests
+    ncal = min(24, len(trace))
+    with serve.Server(budget, max_slots=4, chunk_steps=args.chunk, storage=args.storage) as s:
+        ids = [s.enqueue(r["params"], serve_init(r["geo"]), min(r["steps"], 2000)) for r in trace[:ncal]]
+        res = [s.wait(i) for i in ids]
+        st = s.stats()
+    cal_span = max(r["t_done"] for r in res) - min(r["t_arrive"] for r in res)
+    capacity = st["lattice_updates"] / cal_span / 1e6
+    lam = args.load * capacity * 1e6 / lu.mean()            # requests per second
+    arrive = np.cumsum([r["gap"] for r in trace]) / lam
+    log(f"serve: capacity {capacity:.0f} MLUPS at 4 concurrent, lambda {lam:.2f}/s, "
+        f"trace span {arrive[-1]:.1f} s, {lu.sum():.3e} LU")
+
+    # served run, arrivals in real time
+    srv = serve.Server(budget, max_slots=args.max_slots, chunk_steps=args.chunk, storage=args.storage)
+    ids = [None] * len(trace)
+    t0 = time.perf_counter()
+
+    def client():
+        for i, r in enumerate(trace):
+            dt = t0 + arrive[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            ids[i] = srv.enqueue(r["params"], serve_init(r["geo"]), r["steps"])
+
+    th = threading.Thread(target=client)
+    th.start()
+    served = []
+    for i in range(len(trace)):
+        while ids[i] is None:
+            time.sleep(0.001)
+        served.append(srv.wait(ids[i]))
+        if (i + 1) % 200 == 0:
+            log(f"serve: {i + 1}/{len(trace)} served, t = {time.perf_counter() - t0:.1f} s")
+    th.join()
+    sst = srv.stats()
+    srv.close()
+    lat = [r["t_done"] - r["t_arrive"] for r in served]
+    span = max(r["t_done"] for r in served) - min(r["t_arrive"] for r in served)
+    ok = [r["status"] == capi.LBM_OK for r in served]
+
+    # serial FP32 baseline on the single-lattice path
+    stream = torch.cuda.Stream()
+    sid = stream.cuda_stream
+    service, serial_diag, mass0 = [], [], []
+    for i, r in enumerate(trace):
+        p = dict(r["params"], storage="f32")
+        rr, rb = W.geo_fields(r["geo"], p["nx"], p["ny"])
+        mass0.append((float(rr.sum()), float(rb.sum())))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lat32 = capi.Lattice(p, stream=sid)
+        lat32.init(rr, rb)
+        lat32.step(r["steps"])
+        d = lat32.diag(check=False)
+        if r["kind"] == "bubble" and d["n_nonfinite"] == 0 and d["area_r"] > 0:
+            R = math.sqrt(d["area_r"] / math.pi)
+            d = lat32.diag(circle=(r["geo"]["cx"], r["geo"]["cy"], R - 4.0, R + 4.0), check=False)
+        lat32.close()
+        service.append(time.perf_counter() - t)
+        serial_diag.append(d)
+        if (i + 1) % 200 == 0:
+            log(f"serial fp32: {i + 1}/{len(trace)} solved, {sum(service):.1f} s of solve time")
+    done, lat_serial = 0.0, []
+    for a, sv in zip(arrive, service):
+        done = max(a, done) + sv
+        lat_serial.append(done - a)
+    serial_span = done - arrive[0]
+
+    # Laplace jump and colour mass of the served 16-bit results against FP32
+    dpdiff, mdrift16, mdrift32, unstable16, unstable32 = [], [], [], 0, 0
+    for r, a, b, (m_r, m_b) in zip(trace, served, serial_diag, mass0):
+        da = a["diag"]
+        unstable16 += int(a["status"] != capi.LBM_OK)
+        unstable32 += int(b["n_nonfinite"] > 0)
+        if a["status"] != capi.LBM_OK or b["n_nonfinite"] > 0:
+            continue
+        for dd, acc in ((da, mdrift16), (b, mdrift32)):
+            acc.append(max(abs(dd["mass_r"] / m_r - 1.0) if m_r else 0.0,
+                           abs(dd["mass_b"] / m_b - 1.0) if m_b else 0.0))
+        x, y = dp_of(da, r), dp_of(b, r)
+        if x is not None and y is not None:
+            dpdiff.append(abs(x[0] - y[0]) / y[1])
+    bub = sum(1 for r in trace if r["kind"] == "bubble")
+    return dict(
+        value=lu.sum() / span / 1e6,
+        steps=len(trace),
+        ms_per_step=span * 1e3 / len(trace),
+        workload=f"serving mix: {len(trace)} Poisson-arriving solves ({bub} static bubbles, "
+                 f"{len(trace) - bub} gravity slugs), 64^2..1024^2 nodes, 1000..50000 steps, "
+                 f"gamma in {{1,10,100,1000}}",
+        serving=dict(
+            requests=len(trace), lambda_per_s=lam, load=args.load, capacity_mlups=capacity,
+            storage=args.storage, chunk_steps=args.chunk, max_slots=args.max_slots,
+            hbm_budget_gib=args.hbm_budget_gib, lattice_updates=float(lu.sum()),
+            p50_s=pct(lat, 50), p99_s=pct(lat, 99), mean_s=float(np.mean(lat)), makespan_s=span,
+            aggregate_mlups=lu.sum() / span / 1e6,
+            busy_mlups=sst["lattice_updates"] / sst["busy_s"] / 1e6 if sst["busy_s"] else None,
+            busy_frac=sst["busy_s"] / span, chunks=sst["chunks"], peak_active=sst["peak_active"],
+            peak_bytes=sst["peak_bytes"], unstable=unstable16, completed_ok=int(sum(ok)),
+            serial_fp32=dict(p50_s=pct(lat_serial, 50), p99_s=pct(lat_serial, 99),
+                             mean_s=float(np.mean(lat_serial)), makespan_s=serial_span,
+                             aggregate_mlups=lu.sum() / serial_span / 1e6,
+                             solve_mlups=lu.sum() / sum(service) / 1e6, unstable=unstable32),
+            laplace_dp_vs_fp32=dict(n=len(dpdiff), max=max(dpdiff) if dpdiff else None,
+                                    p99=pct(dpdiff, 99), median=pct(dpdiff, 50),
+                                    over_1pct=int(sum(d > 0.01 for d in dpdiff))),
+            mass_drift=dict(served_max=max(mdrift16) if mdrift16 else None,
+                            fp32_max=max(mdrift32) if mdrift32 else None),
+        ),
+        first_bubble=next(r for r in trace if r["kind"] == "bubble"),
+        budget_bytes=budget,
+    )
+
+
+def main_serve(args, log):
+    from paper_1903_01168_amd import workloads as W
+    t0 = time.perf_counter()
+    r = run_serve(args, log)
+    wall = time.perf_counter() - t0
+    sv = r["serving"]
+    bpu = bytes_per_update(args.storage)
+    cpu = None
+    if not args.no_cpu_baseline:
+        fb = r["first_bubble"]
+        p = dict(fb["params"])
+        rr, rb = W.geo_fields(fb["geo"], p["nx"], p["ny"])
+        cpu = cpu_baseline(dict(params=p, rho_r=rr, rho_b=rb, ux=None, uy=None,
+                                name=f"bubble gamma={fb['gamma']}"), args.cpu_seconds)
+    out = {
+        "metric": "MLUPS & HBM GB/s (% of peak), color-gradient D2Q9; p50/p99 solve latency",
+        "value": r["value"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": r["steps"],
+        "warmup": 0,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "f32" else f"f32 arithmetic, {args.storage} storage",
+        "data": "synthetic (seeded)",
+        "config": {"workload": r["workload"], "storage": args.storage, "seed": args.seed,
+                   "step": "one request solved to completion (value: lattice updates / makespan)",
+                   "launch": f"batched k_step over all active lattices, HIP-graph chunks of {args.chunk}"},
+        "roofline": {"bound": "hbm", "achieved": sv["busy_mlups"] * bpu / 1e3 if sv["busy_mlups"] else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sv["busy_mlups"] * bpu / 1e3 / HBM_PEAK_GBS if sv["busy_mlups"] else None,
+                     "traffic": None, "bytes_per_update": bpu, "kernel": "k_step",
+                     "note": "lattice updates / time spent in chunks (chunk set-up included)"},
+        "cpu_baseline": cpu,
+        "serving": sv,
+        "wall_s": wall,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="sweep512")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "bf16s"])
+    ap.add_argument("--storage", default=None, choices=["f32", "f16s", "bf16s"],
+                    help="population storage (default f32; f16s for the serving mix)")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--strip", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the storage-precision report (converged 64x64 bubble vs the FP64 oracle)")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--load", type=float, default=0.8, help="serve: offered load / measured capacity")
+    ap.add_argument("--chunk", type=int, default=100, help="serve: steps per chunk")
+    ap.add_argument("--max-slots", type=int, default=256, help="serve: lattices advanced together")
+    ap.add_argument("--hbm-budget-gib", type=float, default=64.0, help="serve: device memory budget")
     ap.add_argument("--copy-only", type=float, default=0.0,
                     help="only time the plain copy kernel over this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -117,6 +358,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.storage is None:
+        args.storage = "f16s" if args.workload == "serve" else "f32"
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    if args.workload == "serve":
+        main_serve(args, log)
+        return
 
     import numpy as np
     import torch
@@ -200,6 +451,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cells[0], args.cpu_seconds)
+    precision = None if args.no_precision else precision_report(sid)
 
     p0 = cells[0]["params"]
     out = {
@@ -223,6 +475,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_update": bpu, "kernel": "k_step", "kernel_hash": kernel_hash()},
         "cpu_baseline": cpu,
+        "precision": precision,
         "wall_s": wall,
         "cells": cells_out,
     }

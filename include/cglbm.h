@@ -51,9 +51,12 @@ extern "C" {
  * BOUNCEBACK (no-slip walls half-way outside the first/last row). */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_ZOUHE_VELOCITY = 2, LBM_BC_ZOUHE_PRESSURE = 3 };
 enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
-/* Population storage.  Arithmetic is FP32 in every mode.  F16S / BF16S store
- * each population as a 16-bit deviation (N/rho0_k - phi~_k,i) * 2^s from the
- * rest state of its colour, phi~ being phi rounded to the 16-bit format. */
+/* Population storage.  Arithmetic is FP32 in every mode.  F32: 72 B per
+ * node and buffer.  F16S / BF16S store the eight moving populations of each
+ * colour as 16-bit deviations (N/rho0_k - phi~_k,i) * 2^s from the rest state
+ * of the colour (phi~ = phi rounded to the 16-bit format; stochastic
+ * rounding), and the rest population in FP32, holding the node's exact
+ * colour-mass remainder: 40 B per node and buffer. */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16S = 1, LBM_STORE_BF16S = 2 };
 
 typedef struct {
@@ -92,7 +95,8 @@ const char *lbm_last_error(const lbm_ctx *ctx);
 /* Device bytes a context needs for these parameters: two population buffers
  * plus the field staging area.  Returns 0 for invalid parameters. */
 size_t lbm_bytes_required(const lbm_params *p);
-/* Bytes of one population buffer (18 planes, row pitch padded to 64 nodes). */
+/* Bytes of one population buffer (both colours; row pitch padded to 64
+ * nodes; 72 B per node in F32, 40 B with 16-bit storage). */
 size_t lbm_buffer_bytes(const lbm_params *p);
 
 /* Create a context on the current device.  hip_stream: a hipStream_t, or NULL

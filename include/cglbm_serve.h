@@ -55,7 +55,9 @@ typedef struct {
     int32_t slot;          /* slot index it ran in (-1 if never admitted)                       */
     int64_t steps_done;
     double t_arrive, t_admit, t_done;   /* seconds since the server was created                  */
-    lbm_diag_t diag;       /* FP64 diagnostics of the final state                               */
+    lbm_diag_t diag;       /* FP64 diagnostics of the final state; for a DISK request p_in and  */
+                           /* p_out are the mean pressures at r < R - 4 and r > R + 4 around    */
+                           /* (cx, cy), R = sqrt(area_r / pi) (Laplace sampling, Sec. 4)        */
     double *rho_r, *rho_b, *ux, *uy, *p; /* caller-owned [ny][nx] outputs, or NULL; filled when  */
                                          /* the request finished and was enqueued with fields   */
 } lbm_result;

@@ -58,11 +58,12 @@ int validate(const lbm_params *p, std::string &msg)
     if (!p) { msg = "params is NULL"; return LBM_E_INVAL; }
     if (p->nx < 1 || p->ny < 1) { msg = "nx and ny must be >= 1"; return LBM_E_INVAL; }
     {
-        // one colour half (9 planes) of a buffer must stay below 4 GiB: kernels
-        // address it with 32-bit buffer offsets
+        // one colour half of a buffer (9 populations: 36 B per node in FP32,
+        // 20 B with 16-bit storage) must stay below 4 GiB: kernels address it
+        // with 32-bit buffer offsets
         const long long pitch = (p->nx + 63) / 64 * 64;
-        const long long elem = p->storage == LBM_STORE_F32 ? 4 : 2;
-        if (9 * pitch * p->ny * elem >= (1LL << 32) - 4096) { msg = "lattice too large"; return LBM_E_INVAL; }
+        const long long per_node = p->storage == LBM_STORE_F32 ? 36 : 20;
+        if (per_node * pitch * p->ny >= (1LL << 32) - 4096) { msg = "lattice too large"; return LBM_E_INVAL; }
     }
     const bool xper = p->bc_xlo == LBM_BC_PERIODIC || p->bc_xhi == LBM_BC_PERIODIC;
     if (xper && !(p->bc_xlo == LBM_BC_PERIODIC && p->bc_xhi == LBM_BC_PERIODIC)) {
@@ -101,23 +102,10 @@ Layout layout(const lbm_params *p)
     L.elem = p->storage == LBM_STORE_F32 ? 4 : 2;
     L.pitch = (p->nx + 63) / 64 * 64;
     L.plane = (long long)L.pitch * p->ny;
-    L.buf_bytes = (size_t)L.plane * 18 * L.elem;
+    // FP32: 18 planes of 4 B.  16-bit: per colour an FP32 rest plane and
+    // eight 16-bit planes (20 B per node and colour)
+    L.buf_bytes = (size_t)L.plane * (p->storage == LBM_STORE_F32 ? 72 : 40);
     return L;
-}
-
-static float round_to_storage(double v, int storage)
-{
-    if (storage == LBM_STORE_F16S) return (float)(_Float16)(float)v;
-    if (storage == LBM_STORE_BF16S) {
-        float f = (float)v;
-        uint32_t b;
-        std::memcpy(&b, &f, 4);
-        b += 0x7fffu + ((b >> 16) & 1u);
-        b &= 0xffff0000u;
-        std::memcpy(&f, &b, 4);
-        return f;
-    }
-    return (float)v;
 }
 
 // Derived constants of Sec. 2.1.1 (alpha from equal reference pressures,
@@ -129,29 +117,28 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
     const double ab = p->rho0_r <= p->rho0_b ? 1.0 - (1.0 - p->alpha_light) * p->rho0_r / p->rho0_b : p->alpha_light;
     const double alpha[2] = {ar, ab};
     const double rho0[2] = {p->rho0_r, p->rho0_b};
-    const int s_shift = p->storage == LBM_STORE_F16S ? 12 : 0;
-    const double two_s = std::ldexp(1.0, s_shift);
     for (int k = 0; k < 2; ++k) {
         const double ph[3] = {alpha[k], (1.0 - alpha[k]) / 5.0, (1.0 - alpha[k]) / 20.0};
         d.rho0[k] = (float)rho0[k];
         d.inv_rho0[k] = (float)(1.0 / rho0[k]);
         d.cs2[k] = (float)(3.0 * (1.0 - alpha[k]) / 5.0);
         d.rho_out[k] = (float)(p->p_out / (3.0 * (1.0 - alpha[k]) / 5.0));
-        d.enc_scale[k] = (float)(two_s / rho0[k]);
         // FP32 weights; the residual of their unit sum is carried separately so
         // that the equilibrium holds exactly the node's mass (no drift per step)
         const float f1 = (float)ph[1], f2 = (float)ph[2];
         const float f0 = (float)(1.0 - 4.0 * (double)f1 - 4.0 * (double)f2);
         d.phi0_eps[k] = (float)(1.0 - (double)f0 - 4.0 * (double)f1 - 4.0 * (double)f2);
         const float fc[3] = {f0, f1, f2};
-        for (int c = 0; c < 3; ++c) {
-            d.phi[k][c] = fc[c];
-            const float pt = round_to_storage(ph[c], p->storage);
-            d.phit[k][c] = p->storage == LBM_STORE_F32 ? 0.f : pt;
-            d.enc_off[k][c] = p->storage == LBM_STORE_F32 ? 0.f : (float)(pt * two_s);
-        }
+        for (int c = 0; c < 3; ++c) d.phi[k][c] = fc[c];
+        d.rest0[k] = (float)(rho0[k] * ph[0]);
     }
-    d.dec_mul = (float)(1.0 / two_s);
+    // 16-bit storage: reference population of a moving class, rho0_k phi^k_c
+    // (the same for both fluids: rho0_k (1 - alpha_k) is), and the deviation
+    // scale (unused in FP32 storage)
+    for (int c = 0; c < 3; ++c)
+        d.mref[c] = c == 0 ? 0.f : (float)(rho0[0] * (1.0 - alpha[0]) / (c == 1 ? 5.0 : 20.0));
+    d.dscale = (float)std::ldexp(1.0 / std::max(rho0[0], rho0[1]), 12);
+    d.dmul = (float)(std::max(rho0[0], rho0[1]) * std::ldexp(1.0, -12));
     const double wr = 1.0 / p->tau_r, wb = 1.0 / p->tau_b, del = p->delta;
     const double chi = 2.0 * wr * wb / (wr + wb);
     const double eta = 2.0 * (wr - chi) / del;

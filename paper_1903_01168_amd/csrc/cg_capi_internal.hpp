@@ -14,10 +14,10 @@
 namespace cgi {
 
 struct Layout {
-    int elem = 4;            // bytes per stored population
+    int elem = 4;            // bytes per stored moving population
     int pitch = 0;           // row pitch in elements (multiple of 64)
     long long plane = 0;     // elements per plane
-    size_t buf_bytes = 0;    // one buffer: 18 planes
+    size_t buf_bytes = 0;    // one buffer: both colours, 9 populations each
 };
 
 }  // namespace cgi

@@ -38,7 +38,7 @@ enum : int { ST_F32 = 0, ST_F16S = 1, ST_BF16S = 2 };
 struct SlotDesc {
     void *buf[2];                 // population buffers; a launch reads buf[parity]
     const int8_t *inlet_color;    // [ny], +1 red / -1 blue (open x only)
-    long long plane;              // elements between two of the 18 planes
+    long long plane;              // nodes per plane (pitch * ny)
     int nx, ny, pitch;            // lattice size, row pitch in elements
     int strip, tiles_x, tiles_y;  // rows per workgroup strip, tile grid
     int tile_begin;               // first tile of this slot in the launch
@@ -57,10 +57,10 @@ struct SlotDesc {
     float u_in[2];                // inlet velocity by colour
     float rho_out[2];             // p_out / c_s,k^2
     float cs2[2];
-    float enc_scale[2];           // 2^s / rho0_k            (16-bit storage)
-    float enc_off[2][3];          // phi~ 2^s by class
-    float dec_mul;                // 2^-s
-    float phit[2][3];             // phi~ by class
+    // 16-bit storage (see the codec below):
+    float mref[3];                // rho0_k phi^k_c by class c ([0] unused)
+    float dscale, dmul;           // deviation scale 2^12 / max(rho0) and its inverse
+    float rest0[2];               // rho0_k phi^k_0: reference of the FP32 rest population
 };
 
 // ------------------------------------------------------------------ codec --
@@ -102,8 +102,48 @@ template <> struct Codec<ST_F32> {
     }
 };
 
-// 16-bit shifted storage: q = (N / rho0_k - phi~) 2^s, N = rho0_k (phi~ + q 2^-s).
-// An absent colour (N = 0) encodes to -phi~ 2^s exactly and decodes to 0.
+// ----------------------------------------------------- 16-bit storage --
+// A moving population pair (N^r_i, N^b_i) is stored as two 16-bit values:
+//   u = round(65535 g), g = N^r_i / N_i the red share of the colour-blind
+//       population N_i = N^r_i + N^b_i (exactly 0 or 1 where a colour is absent);
+//   q = (N_i - m_c) 2^12 / max(rho0) as FP16 (or BF16), the deviation of N_i
+//       from m_c = rho0_r phi^r_c = rho0_b phi^b_c, the population of the
+//       direction's class at rest at the reference density of either fluid
+//       (equal for both fluids: the phases' alphas make rho0_k (1 - alpha_k)
+//       the same, Sec. 2.1.1).
+// Decoding: N_i = m_c + q 2^-12 max(rho0), N^r_i = g N_i, N^b_i = (1 - g) N_i.
+// The colour-blind population, which carries mass and momentum, is held as a
+// small deviation with FP16's relative precision in bulk and interface nodes
+// alike, and the colour split with a uniform 1.5e-5 quantum; a per-colour
+// encoding would quantise interface populations to ~1e-4 rho0, which feeds
+// spurious currents of ~1e-3 and shifts the Laplace jump by tens of percent.
+// The rest population of each colour is stored in FP32 and takes the node's
+// exact colour-mass remainder (see store18).  Rounding is stochastic, with a
+// dither drawn from a hash of the node position and of the values being
+// stored (deterministic: the same inputs give the same bits, whatever else
+// runs in the launch): round-to-nearest would repeat the same error at a
+// steady node every step.
+#ifndef CG_CODEC_SR
+#define CG_CODEC_SR 1
+#endif
+
+// 32-bit integer finaliser (xor-shift / multiply, "lowbias32" of C. Wellons).
+__device__ __forceinline__ uint32_t mix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h;
+}
+// next dither: linear congruential step (Numerical Recipes constants); its
+// high bits are the random ones
+__device__ __forceinline__ uint32_t lcg(uint32_t s) { return s * 1664525u + 1013904223u; }
+
+typedef _Float16 cg_h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 cg_b2 __attribute__((ext_vector_type(2)));
+
 template <> struct Codec<ST_F16S> {
     using Raw = uint16_t;
     static constexpr int bytes = 2;
@@ -111,16 +151,20 @@ template <> struct Codec<ST_F16S> {
     {
         return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, CG_LOAD_POLICY);
     }
-    static __device__ __forceinline__ float dec(Raw v, const SlotDesc &S, int k, int c)
+    static __device__ __forceinline__ void put(Raw q, Rsrc r, uint32_t voff, uint32_t soff)
     {
-        return S.rho0[k] * __builtin_fmaf((float)__builtin_bit_cast(_Float16, v), S.dec_mul, S.phit[k][c]);
+        __builtin_amdgcn_raw_buffer_store_b16(q, r, (int)voff, (int)soff, CG_STORE_POLICY);
     }
-    static __device__ __forceinline__ void store(float v, Rsrc r, uint32_t voff, uint32_t soff, const SlotDesc &S,
-                                                 int k, int c)
+    static __device__ __forceinline__ float dec_q(Raw v) { return (float)__builtin_bit_cast(_Float16, v); }
+    // gfx950 conversion with stochastic rounding; it takes its random bits
+    // from the high end of the 32-bit operand
+    static __device__ __forceinline__ Raw enc_q(float q, uint32_t rnd)
     {
-        const _Float16 q = (_Float16)__builtin_fmaf(v, S.enc_scale[k], -S.enc_off[k][c]);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, q), r, (int)voff, (int)soff, CG_STORE_POLICY);
+        if (!CG_CODEC_SR) return __builtin_bit_cast(uint16_t, (_Float16)q);
+        const cg_h2 r = __builtin_amdgcn_cvt_sr_f16_f32((cg_h2){0, 0}, q, rnd, false);
+        return __builtin_bit_cast(uint16_t, r[0]);
     }
+    static __device__ __forceinline__ Raw enc_q_nearest(float q) { return __builtin_bit_cast(uint16_t, (_Float16)q); }
 };
 
 template <> struct Codec<ST_BF16S> {
@@ -130,23 +174,117 @@ template <> struct Codec<ST_BF16S> {
     {
         return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, CG_LOAD_POLICY);
     }
-    static __device__ __forceinline__ float dec(Raw v, const SlotDesc &S, int k, int c)
+    static __device__ __forceinline__ void put(Raw q, Rsrc r, uint32_t voff, uint32_t soff)
     {
-        const float q = __uint_as_float((uint32_t)v << 16);
-        return S.rho0[k] * __builtin_fmaf(q, S.dec_mul, S.phit[k][c]);
+        __builtin_amdgcn_raw_buffer_store_b16(q, r, (int)voff, (int)soff, CG_STORE_POLICY);
     }
-    static __device__ __forceinline__ void store(float v, Rsrc r, uint32_t voff, uint32_t soff, const SlotDesc &S,
-                                                 int k, int c)
+    static __device__ __forceinline__ float dec_q(Raw v) { return __uint_as_float((uint32_t)v << 16); }
+    static __device__ __forceinline__ Raw enc_q_nearest(float q)
     {
-        const float q = __builtin_fmaf(v, S.enc_scale[k], -S.enc_off[k][c]);
         uint32_t b = __float_as_uint(q);
         if ((b & 0x7f800000u) == 0x7f800000u) b = b | ((b & 0xffffu) ? 0x400000u : 0u);   // keep NaN a NaN
         else b += 0x7fffu + ((b >> 16) & 1u);                                             // round to nearest even
-        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(b >> 16), r, (int)voff, (int)soff, CG_STORE_POLICY);
+        return (Raw)(b >> 16);
+    }
+    static __device__ __forceinline__ Raw enc_q(float q, uint32_t rnd)
+    {
+        if (!CG_CODEC_SR) return enc_q_nearest(q);
+        const cg_b2 r = __builtin_amdgcn_cvt_sr_bf16_f32((cg_b2){0, 0}, q, rnd, false);
+        return __builtin_bit_cast(uint16_t, r[0]);
     }
 };
 
-// The two colour halves (9 planes each) of one population buffer.
+// red share of a stored pair: u / 65535 (to within 2e-10; exactly 0 and 1 at
+// the ends), and the blue share from 65535 - u in the same way
+__device__ __forceinline__ float share(uint32_t u)
+{
+    const float f = (float)u;
+    return __builtin_fmaf(f, 0x1p-32f, f * 0x1p-16f);
+}
+template <int ST>
+__device__ __forceinline__ void dec_pair(const SlotDesc &S, int c, uint16_t q, uint16_t u, float &N, float &nr, float &nb)
+{
+    const float gr = share(u), gb = share(65535u - u);
+    N = __builtin_fmaf(Codec<ST>::dec_q(q), S.dmul, S.mref[c]);
+    nr = gr * N;
+    nb = gb * N;
+}
+
+// Encode a pair; returns the decoded values the store leaves behind.
+// rnd: dither (high bits for the deviation, low 16 bits for the share);
+// sr = false: round to nearest.
+template <int ST>
+__device__ __forceinline__ void enc_pair(const SlotDesc &S, int c, float vr, float vb, uint32_t rg, uint32_t rq, bool sr,
+                                         uint16_t &q, uint16_t &u, float &nr, float &nb)
+{
+    const float n = vr + vb;
+    float g = vr * __builtin_amdgcn_rcpf(n);
+    g = g > 0.f ? (g < 1.f ? g : 1.f) : 0.f;          // NaN -> 0 (its N stays NaN)
+    g = vb == 0.f ? 1.f : (vr == 0.f ? 0.f : g);       // an absent colour stays exactly absent
+    const float dith = sr ? (float)(rg >> 16) * 0x1p-16f : 0.5f;
+    const uint32_t ui = (uint32_t)__builtin_fmaf(g, 65535.f, dith);   // g in [0,1]: 0 .. 65535
+    u = (uint16_t)(ui > 65535u ? 65535u : ui);
+    const float gr = share(u), gb = share(65535u - u);
+    const float x = (n - S.mref[c]) * S.dscale;
+    q = sr ? Codec<ST>::enc_q(x, rq) : Codec<ST>::enc_q_nearest(x);
+    const float N = __builtin_fmaf(Codec<ST>::dec_q(q), S.dmul, S.mref[c]);
+    nr = gr * N;
+    nb = gb * N;
+}
+
+// FP32 rest population of a colour: the value itself or its deviation from
+// rest0, whichever is smaller in magnitude (finer FP32 quantum for a minority
+// and for a majority colour alike); the mantissa's last bit tells which.  The
+// value is rounded onto the FP32 numbers that carry that last bit (a grid of
+// two ulps), stochastically with the dither r01 in [0, 1) (0.5: to nearest):
+// forcing the bit onto a rounded value would bias the rest, and with it the
+// colour mass, at every node and step.
+__device__ __forceinline__ uint32_t enc_rest(double v, float ref, double r01)
+{
+    const uint32_t flag = fabs(v - (double)ref) < fabs(v) ? 1u : 0u;
+    const double t = flag ? v - (double)ref : v;
+    const double a = fabs(t);
+    const uint32_t m = __float_as_uint((float)a);
+    uint32_t lo, hi;
+    if ((m & 1u) == flag) {
+        if ((double)__uint_as_float(m) <= a) { lo = m; hi = m + 2u; }
+        else { lo = m - 2u; hi = m; }
+    } else {
+        lo = m - 1u;
+        hi = m + 1u;
+    }
+    if (lo > hi) lo = flag;   // below the smallest magnitude of the grid
+    const double vlo = (double)__uint_as_float(lo), vhi = (double)__uint_as_float(hi);
+    const uint32_t mm = (a - vlo) > r01 * (vhi - vlo) ? hi : lo;
+    return mm | (t < 0.0 ? 0x80000000u : 0u);
+}
+// decoded rest population (FP32) and its exact value (FP64)
+__device__ __forceinline__ float dec_rest(uint32_t b, float ref, double &exact)
+{
+    const float x = __uint_as_float(b);
+    const bool dev = b & 1u;
+    exact = (double)x + (dev ? (double)ref : 0.0);
+    return dev ? x + ref : x;
+}
+
+// Layout of one colour half of a population buffer.  FP32: nine planes of
+// 4-byte values, direction i at byte i * pb (pb = 4 * plane).  16-bit
+// storage: the rest population (direction 0, which does not stream) as an
+// FP32 plane of 2 * pb bytes first, then the eight moving populations as
+// 16-bit planes, direction i >= 1 at byte (i + 1) * pb (pb = 2 * plane).
+// The FP32 rest population carries each node's exact colour-mass residual
+// (see store18), which 16-bit values cannot hold.
+template <int ST> __host__ __device__ constexpr bool rest32() { return ST != ST_F32; }
+template <int ST> __device__ __forceinline__ uint32_t plane_off(int i, uint32_t pb)
+{
+    return rest32<ST>() ? (i == 0 ? 0u : (uint32_t)(i + 1) * pb) : (uint32_t)i * pb;
+}
+template <int ST> __device__ __forceinline__ long long half_bytes(long long plane)
+{
+    return rest32<ST>() ? 20ll * plane : 9ll * plane * Codec<ST>::bytes;
+}
+
+// The two colour halves of one population buffer.
 struct Halves {
     Rsrc r[2];
 };
@@ -154,9 +292,18 @@ struct Halves {
 template <int ST>
 __device__ __forceinline__ Halves halves(const SlotDesc &S, const void *buf)
 {
-    const uint32_t half = (uint32_t)(9ll * S.plane * Codec<ST>::bytes);
+    const uint32_t half = (uint32_t)half_bytes<ST>(S.plane);
     const char *b = reinterpret_cast<const char *>(buf);
     return Halves{{make_rsrc(b, half), make_rsrc(b + half, half)}};
+}
+
+__device__ __forceinline__ uint32_t load_f32raw(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, CG_LOAD_POLICY);
+}
+__device__ __forceinline__ void store_f32(float v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, CG_STORE_POLICY);
 }
 
 // ------------------------------------------------------------ node state --
@@ -171,9 +318,11 @@ struct Node {
 // columns x+1, x, x-1), with periodic wrap or, at an open face, a clamp (the
 // value read there is a placeholder that the Zou-He completion overwrites).
 struct XCols {
-    uint32_t off[3];
-    int x;          // the lane's own column (in range)
+    uint32_t om, o0, op;   // sources for c_x = -1, 0, +1 (named, not an array: no
+                           // dynamically indexed copy on the private stack)
+    int x;                 // the lane's own column (in range)
     bool inlet, outlet;
+    __device__ __forceinline__ uint32_t col(int d) const { return d < 0 ? om : (d == 0 ? o0 : op); }
 };
 
 __device__ __forceinline__ int wrapi(int v, int n)
@@ -193,7 +342,10 @@ __device__ __forceinline__ XCols make_cols(const SlotDesc &S, int x)
         int sx = x - d;
         if (per) sx = wrapi(sx, S.nx);
         else sx = sx < 0 ? 0 : (sx >= S.nx ? S.nx - 1 : sx);
-        c.off[d + 1] = (uint32_t)sx * Codec<ST>::bytes;
+        const uint32_t o = (uint32_t)sx * Codec<ST>::bytes;
+        if (d < 0) c.om = o;
+        else if (d == 0) c.o0 = o;
+        else c.op = o;
     }
     const bool open = S.flags & F_XOPEN;
     c.inlet = open && x == 0;
@@ -230,7 +382,8 @@ __device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y)
 // Raw (undecoded) populations of one node: issued first, consumed later, so
 // the loads of a row are in flight while the previous row collides.
 template <int ST> struct Raw18 {
-    typename Codec<ST>::Raw v[18];
+    typename Codec<ST>::Raw v[18];   // 16-bit storage: v[i] deviation, v[9 + i] share (i >= 1)
+    uint32_t r0[2];                  // 16-bit storage: FP32 rest populations (v[0], v[9] unused)
 };
 
 template <int ST>
@@ -243,10 +396,14 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
     for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
+            if (rest32<ST>() && i == 0) {   // own node, FP32 plane: offsets twice the 16-bit ones
+                raw.r0[k] = load_f32raw(h.r[k], 2u * xc.o0, 2u * rw.off[1]);
+                continue;
+            }
             const int dy = cy(i) + 1;
             // bounce-back: the node's own opposite population (same row and column)
-            const uint32_t soff = rw.wall[dy] ? (uint32_t)opp(i) * pb + rw.off[1] : (uint32_t)i * pb + rw.off[dy];
-            const uint32_t voff = rw.wall[dy] ? xc.off[1] : xc.off[cx(i) + 1];
+            const uint32_t soff = rw.wall[dy] ? plane_off<ST>(opp(i), pb) + rw.off[1] : plane_off<ST>(i, pb) + rw.off[dy];
+            const uint32_t voff = rw.wall[dy] ? xc.o0 : xc.col(cx(i));
             raw.v[k * 9 + i] = C::load(h.r[k], voff, soff);
         }
     return raw;
@@ -264,16 +421,36 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
     Node nd;
     double rho[2];   // colour masses, exact (nine FP32 values sum exactly in FP64)
     float kn[2];
+    if constexpr (rest32<ST>()) {
+        const float r0 = dec_rest(raw.r0[0], S.rest0[0], rho[0]);
+        const float b0 = dec_rest(raw.r0[1], S.rest0[1], rho[1]);
+        nd.n[0] = r0 + b0;
+        kn[0] = r0;
+        kn[1] = b0;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        rho[k] = 0.0;
-        kn[k] = 0.f;
+        for (int i = 1; i < 9; ++i) {
+            float N, nr, nb;
+            dec_pair<ST>(S, vclass(i), raw.v[i], raw.v[9 + i], N, nr, nb);
+            nd.n[i] = N;
+            rho[0] += (double)nr;
+            rho[1] += (double)nb;
+            if (cx(i) >= 0) {   // the six populations that come from x-1 or x
+                kn[0] += nr;
+                kn[1] += nb;
+            }
+        }
+    } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const float v = C::dec(raw.v[k * 9 + i], S, k, vclass(i));
-            nd.n[i] = (k == 0) ? v : nd.n[i] + v;
-            rho[k] += (double)v;
-            if (cx(i) >= 0) kn[k] += v;   // the six populations that come from x-1 or x
+        for (int k = 0; k < 2; ++k) {
+            rho[k] = 0.0;
+            kn[k] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const float v = C::dec(raw.v[k * 9 + i], S, k, vclass(i));
+                rho[k] += (double)v;
+                nd.n[i] = (k == 0) ? v : nd.n[i] + v;
+                if (cx(i) >= 0) kn[k] += v;   // the six populations that come from x-1 or x
+            }
         }
     }
     nd.rr = (float)rho[0];
@@ -335,17 +512,100 @@ __device__ __forceinline__ void conserve(const Node &nd, float *outr, float *out
     }
 }
 
-// Store the 18 post-recolouring populations of one node.
+// Store the 18 post-recolouring populations of one node; mr, mb: the colour
+// masses the node must hold (exact FP64).  16-bit storage: the eight moving
+// pairs are encoded (see the codec), the colour masses of what they decode to
+// summed exactly in FP64, and each FP32 rest population takes the remainder of
+// its colour's mass, so the stored colour masses of the node are exact to the
+// rounding of one FP32 value each.
 template <int ST>
 __device__ __forceinline__ void store18(const SlotDesc &S, const Halves &h, uint32_t voff, uint32_t rowoff,
-                                        const float *outr, const float *outb)
+                                        const float *outr, const float *outb, double mr, double mb)
 {
     using C = Codec<ST>;
     const uint32_t pb = (uint32_t)S.plane * C::bytes;
+    if constexpr (ST == ST_F32) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        C::store(outr[i], h.r[0], voff, (uint32_t)i * pb + rowoff, S, 0, vclass(i));
-        C::store(outb[i], h.r[1], voff, (uint32_t)i * pb + rowoff, S, 1, vclass(i));
+        for (int i = 0; i < 9; ++i) {
+            C::store(outr[i], h.r[0], voff, (uint32_t)i * pb + rowoff, S, 0, vclass(i));
+            C::store(outb[i], h.r[1], voff, (uint32_t)i * pb + rowoff, S, 1, vclass(i));
+        }
+    } else {
+        uint32_t rnd = mix32((voff + rowoff) ^ mix32(__float_as_uint(outr[1]) ^ __float_as_uint(outb[5]) * 0x9e3779b9u));
+        double ar = 0.0, ab = 0.0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const uint32_t rg = lcg(rnd);
+            rnd = lcg(rg);
+            uint16_t q, u;
+            float nr, nb;
+            enc_pair<ST>(S, vclass(i), outr[i], outb[i], rg, rnd, CG_CODEC_SR != 0, q, u, nr, nb);
+            ar += (double)nr;
+            ab += (double)nb;
+            C::put(q, h.r[0], voff, plane_off<ST>(i, pb) + rowoff);
+            C::put(u, h.r[1], voff, plane_off<ST>(i, pb) + rowoff);
+        }
+        const uint32_t r1 = lcg(rnd), r2 = lcg(r1);
+        const double d1 = CG_CODEC_SR ? (double)(r1 >> 8) * 0x1p-24 : 0.5, d2 = CG_CODEC_SR ? (double)(r2 >> 8) * 0x1p-24 : 0.5;
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest(mr - ar, S.rest0[0], d1), h.r[0], (int)(2u * voff), (int)(2u * rowoff),
+                                              CG_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest(mb - ab, S.rest0[1], d2), h.r[1], (int)(2u * voff), (int)(2u * rowoff),
+                                              CG_STORE_POLICY);
+    }
+}
+
+// Store 18 given populations, rounding to nearest without dither, the rest
+// populations as given.
+template <int ST>
+__device__ __forceinline__ void store18_nearest(const SlotDesc &S, const Halves &h, uint32_t voff, uint32_t rowoff,
+                                                const float *outr, const float *outb)
+{
+    using C = Codec<ST>;
+    const uint32_t pb = (uint32_t)S.plane * C::bytes;
+    if constexpr (ST == ST_F32) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            C::store(outr[i], h.r[0], voff, (uint32_t)i * pb + rowoff, S, 0, vclass(i));
+            C::store(outb[i], h.r[1], voff, (uint32_t)i * pb + rowoff, S, 1, vclass(i));
+        }
+    } else {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            uint16_t q, u;
+            float nr, nb;
+            enc_pair<ST>(S, vclass(i), outr[i], outb[i], 0u, 0u, false, q, u, nr, nb);
+            C::put(q, h.r[0], voff, plane_off<ST>(i, pb) + rowoff);
+            C::put(u, h.r[1], voff, plane_off<ST>(i, pb) + rowoff);
+        }
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest((double)outr[0], S.rest0[0], 0.5), h.r[0], (int)(2u * voff),
+                                              (int)(2u * rowoff), CG_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest((double)outb[0], S.rest0[1], 0.5), h.r[1], (int)(2u * voff),
+                                              (int)(2u * rowoff), CG_STORE_POLICY);
+    }
+}
+
+// The 18 stored populations of one node, decoded (colour-major).
+template <int ST>
+__device__ __forceinline__ void load_own(const SlotDesc &S, const Halves &h, uint32_t voff, uint32_t rowoff, float *out)
+{
+    using C = Codec<ST>;
+    const uint32_t pb = (uint32_t)S.plane * C::bytes;
+    if constexpr (ST == ST_F32) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                out[k * 9 + i] = C::dec(C::load(h.r[k], voff, (uint32_t)i * pb + rowoff), S, k, vclass(i));
+    } else {
+        double e;
+        out[0] = dec_rest(load_f32raw(h.r[0], 2u * voff, 2u * rowoff), S.rest0[0], e);
+        out[9] = dec_rest(load_f32raw(h.r[1], 2u * voff, 2u * rowoff), S.rest0[1], e);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            float N;
+            dec_pair<ST>(S, vclass(i), C::load(h.r[0], voff, plane_off<ST>(i, pb) + rowoff),
+                         C::load(h.r[1], voff, plane_off<ST>(i, pb) + rowoff), N, out[i], out[9 + i]);
+        }
     }
 }
 

@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
             float outr[9], outb[9];
             collide(S, cur, p0.c, Fx, Fy, outr, outb);
             if (ST == ST_F32) conserve(cur, outr, outb);   // 16-bit storage rounds far coarser
-            store18<ST>(S, dst, xc.off[1], (uint32_t)y * rowbytes, outr, outb);
+            store18<ST>(S, dst, xc.o0, (uint32_t)y * rowbytes, outr, outb, cur.mr, cur.mb);
         }
         pb = p0;
         p0 = pa;
@@ -194,7 +194,8 @@ __global__ void __launch_bounds__(256) k_init(const SlotDesc *__restrict__ sd, c
                 e[k][i] = rk[k] * (S.phi[k][vclass(i)] + wgt(i) * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
                 if (i == 0) e[k][i] += rk[k] * S.phi0_eps[k];
             }
-        store18<ST>(S, dst, (uint32_t)x * Codec<ST>::bytes, (uint32_t)y * S.pitch * Codec<ST>::bytes, e[0], e[1]);
+        store18<ST>(S, dst, (uint32_t)x * Codec<ST>::bytes, (uint32_t)y * S.pitch * Codec<ST>::bytes, e[0], e[1],
+                    (double)rk[0], (double)rk[1]);
     }
 }
 
@@ -293,16 +294,13 @@ __global__ void __launch_bounds__(256) k_get_pops(const SlotDesc *__restrict__ s
     const SlotDesc S = *sd;
     const long long n = (long long)S.nx * S.ny;
     const Halves src = halves<ST>(S, which ? S.buf[1] : S.buf[0]);
-    const uint32_t pb = (uint32_t)S.plane * C::bytes;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(c / S.nx), x = (int)(c - (long long)y * S.nx);
-        const uint32_t voff = (uint32_t)x * C::bytes, roff = (uint32_t)y * S.pitch * C::bytes;
+        float v[18];
+        load_own<ST>(S, src, (uint32_t)x * C::bytes, (uint32_t)y * S.pitch * C::bytes, v);
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                out[(long long)(k * 9 + i) * n + c] = C::dec(C::load(src.r[k], voff, (uint32_t)i * pb + roff), S, k, vclass(i));
+        for (int j = 0; j < 18; ++j) out[(long long)j * n + c] = v[j];
     }
 }
 
@@ -323,7 +321,7 @@ __global__ void __launch_bounds__(256) k_set_pops(const SlotDesc *__restrict__ s
             r[i] = in[(long long)i * n + c];
             b[i] = in[(long long)(9 + i) * n + c];
         }
-        store18<ST>(S, dst, (uint32_t)x * C::bytes, (uint32_t)y * S.pitch * C::bytes, r, b);
+        store18_nearest<ST>(S, dst, (uint32_t)x * C::bytes, (uint32_t)y * S.pitch * C::bytes, r, b);
     }
 }
 

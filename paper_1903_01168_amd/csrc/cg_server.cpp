@@ -244,6 +244,13 @@ struct GpuBackend : Backend {
         (void)hipSetDevice(device);
         lbm_diag_t d{};
         int rc = lbm_diag(r.ctx, nullptr, &d);
+        if (rc == LBM_OK && r.kind == LBM_INIT_DISK && d.area_r > 0) {
+            // Laplace sampling of a bubble: mean pressure inside r < R - 4 and
+            // outside r > R + 4, R the radius of a disk of the red area
+            const double R = std::sqrt(d.area_r / M_PI);
+            const double circle[4] = {r.geo.cx, r.geo.cy, R - 4.0, R + 4.0};
+            rc = lbm_diag(r.ctx, circle, &d);
+        }
         r.diag = d;
         if (rc == LBM_E_UNSTABLE && r.status == LBM_E_BUSY) r.status = LBM_E_UNSTABLE;
         else if (rc != LBM_OK && r.status == LBM_E_BUSY) r.status = rc;

@@ -71,11 +71,11 @@ def static_bubble(n=64, radius=16.0, A=1e-3, tau=1.0, beta=0.7, collision="bgk",
                 ux=None, uy=None, radius=radius, center=(n / 2, n / 2))
 
 
-def bubble_cell(gamma, M, radius, n=512, tau_min=0.6, sigma=4.0e-3 / 9.0, beta=0.7,
-                collision="bgk", storage="f32"):
-    """One cell of the bubble sweep.  The light fluid is inside and coloured
-    red (rho0_r = 1, rho0_b = gamma).  M is the dynamic-viscosity ratio
-    heavy/light, so nu_heavy / nu_light = M / gamma; the smaller tau is
+def bubble_params(gamma, M, n=512, tau_min=0.6, sigma=4.0e-3 / 9.0, beta=0.7, collision="bgk",
+                  storage="f32"):
+    """Parameters of a periodic n x n bubble lattice with the light fluid
+    coloured red (rho0_r = 1, rho0_b = gamma).  M is the dynamic-viscosity
+    ratio heavy/light, so nu_heavy / nu_light = M / gamma; the smaller tau is
     ``tau_min``.  Surface tension is fixed through sigma (A follows omega)."""
     ratio = M / gamma                       # nu_heavy / nu_light
     if ratio <= 1.0:
@@ -84,8 +84,16 @@ def bubble_cell(gamma, M, radius, n=512, tau_min=0.6, sigma=4.0e-3 / 9.0, beta=0
     else:
         tau_l = tau_min
         tau_h = tau_from_nu(nu_from_tau(tau_l) * ratio)
-    p = params(nx=n, ny=n, rho0_r=1.0, rho0_b=float(gamma), tau_r=tau_l, tau_b=tau_h,
-               sigma=sigma, beta=beta, collision=collision, storage=storage)
+    return params(nx=n, ny=n, rho0_r=1.0, rho0_b=float(gamma), tau_r=tau_l, tau_b=tau_h,
+                  sigma=sigma, beta=beta, collision=collision, storage=storage)
+
+
+def bubble_cell(gamma, M, radius, n=512, tau_min=0.6, sigma=4.0e-3 / 9.0, beta=0.7,
+                collision="bgk", storage="f32"):
+    """One cell of the bubble sweep: ``bubble_params`` plus the light disk of
+    the given radius at the lattice centre."""
+    p = bubble_params(gamma, M, n=n, tau_min=tau_min, sigma=sigma, beta=beta, collision=collision,
+                      storage=storage)
     rr, rb = disk_fields(n, n, n / 2, n / 2, radius, 1.0, float(gamma))
     return dict(name=f"bubble {n}x{n} gamma={gamma} M={M} R={radius}", params=p, rho_r=rr,
                 rho_b=rb, ux=None, uy=None, radius=float(radius), center=(n / 2, n / 2),
@@ -107,9 +115,10 @@ def bubble_sweep(seed=0, n=512, storage="f32", collision="bgk"):
     return cells
 
 
-def slug_bands(nx, rng, lo=200, hi=600):
-    """Alternating heavy/light bands along x with seeded lengths in [lo, hi];
-    the last band absorbs the remainder; an even count of at least two."""
+def slug_edges(nx, rng, lo=200, hi=600):
+    """First columns of alternating heavy/light full-height bands along x,
+    seeded lengths in [lo, hi]; the last band absorbs the remainder; an even
+    count of at least two.  Band b is heavy for even b."""
     edges = [0]
     while True:
         length = int(rng.integers(lo, hi + 1))
@@ -120,6 +129,12 @@ def slug_bands(nx, rng, lo=200, hi=600):
         edges.pop()                         # merge the last two bands
     if len(edges) < 2:
         edges = [0, nx // 2]
+    return edges
+
+
+def slug_bands(nx, rng, lo=200, hi=600):
+    """Heavy-band mask along x of ``slug_edges``."""
+    edges = slug_edges(nx, rng, lo, hi)
     heavy = np.zeros(nx, dtype=bool)
     for b, x0 in enumerate(edges):
         x1 = edges[b + 1] if b + 1 < len(edges) else nx
@@ -127,17 +142,23 @@ def slug_bands(nx, rng, lo=200, hi=600):
     return heavy
 
 
-def gravity_slug(seed=0, nx=4096, ny=256, gamma=10, Re=10, g=1e-6, A=1e-3, beta=0.7,
-                 storage="f32", collision="bgk", band_lo=200, band_hi=600):
-    """Periodic channel with walls top/bottom and a body force along +x.
-    Heavy (red, rho0_r = gamma) and light (blue) full-height slugs.  The heavy
-    viscosity follows Re = g H^3 / (8 nu_l^2) with H = ny; mu_g = mu_l / 2."""
-    rng = np.random.default_rng(seed)
+def slug_params(nx, ny, gamma=10, Re=10, g=1e-6, A=1e-3, beta=0.7, storage="f32", collision="bgk"):
+    """Periodic channel with walls top/bottom and a body force along +x,
+    heavy fluid red (rho0_r = gamma), light blue.  The heavy viscosity follows
+    Re = g H^3 / (8 nu_l^2) with H = ny; mu_g = mu_l / 2."""
     nu_l = math.sqrt(g * ny ** 3 / (8.0 * Re))
     nu_g = nu_l * gamma / 2.0
-    p = params(nx=nx, ny=ny, bc_x="periodic", bc_y="walls", rho0_r=float(gamma), rho0_b=1.0,
-               tau_r=tau_from_nu(nu_l), tau_b=tau_from_nu(nu_g), A=A, beta=beta, gx=g,
-               storage=storage, collision=collision)
+    return params(nx=nx, ny=ny, bc_x="periodic", bc_y="walls", rho0_r=float(gamma), rho0_b=1.0,
+                  tau_r=tau_from_nu(nu_l), tau_b=tau_from_nu(nu_g), A=A, beta=beta, gx=g,
+                  storage=storage, collision=collision)
+
+
+def gravity_slug(seed=0, nx=4096, ny=256, gamma=10, Re=10, g=1e-6, A=1e-3, beta=0.7,
+                 storage="f32", collision="bgk", band_lo=200, band_hi=600):
+    """``slug_params`` with full-height heavy/light slugs of seeded lengths."""
+    rng = np.random.default_rng(seed)
+    p = slug_params(nx, ny, gamma=gamma, Re=Re, g=g, A=A, beta=beta, storage=storage,
+                    collision=collision)
     heavy = slug_bands(nx, rng, band_lo, band_hi)
     rr = np.where(heavy[None, :], float(gamma), 0.0) * np.ones((ny, 1))
     rb = np.where(heavy[None, :], 0.0, 1.0) * np.ones((ny, 1))
@@ -190,3 +211,57 @@ def random_fields(nx, ny, seed=0, rho0_r=1.0, rho0_b=1.0, umax=0.02, smooth=True
     ux = (rng.random((ny, nx)) - 0.5) * 2 * umax
     uy = (rng.random((ny, nx)) - 0.5) * 2 * umax
     return rho_r, rho_b, ux, uy
+
+
+SERVE_GAMMAS = (1, 10, 100, 1000)
+
+
+def serve_trace(seed=0, n=2000, nodes_lo=64 * 64, nodes_hi=1024 * 1024, steps_lo=1000,
+                steps_hi=50000, M=10, Re=10, storage="f16s"):
+    """A seeded mix of solve requests: half static bubbles (square periodic
+    lattice, side a multiple of 64, light disk of radius side/4 at the centre,
+    viscosity ratio M), half periodic gravity slugs (16:1 channel with walls,
+    height a multiple of 16, slugs 200..600 long, Reynolds number Re).  Node
+    counts and step counts are log-uniform in their ranges, the density ratio
+    is drawn from SERVE_GAMMAS, and ``gap`` is a unit-mean exponential
+    inter-arrival draw (divide by the arrival rate)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        bubble = bool(rng.random() < 0.5)
+        nodes = math.exp(rng.uniform(math.log(nodes_lo), math.log(nodes_hi)))
+        gamma = int(rng.choice(SERVE_GAMMAS))
+        steps = int(round(math.exp(rng.uniform(math.log(steps_lo), math.log(steps_hi)))))
+        gap = float(rng.exponential(1.0))
+        sub = int(rng.integers(1 << 62))
+        if bubble:
+            side = int(min(1024, max(64, 64 * round(math.sqrt(nodes) / 64))))
+            p = bubble_params(gamma, M, n=side, storage=storage)
+            geo = dict(kind="disk", cx=side / 2, cy=side / 2, radius=side / 4, rho_r_in=1.0, rho_b_in=0.0,
+                       rho_r_out=0.0, rho_b_out=float(gamma))
+        else:
+            ny = int(min(256, max(16, 16 * round(math.sqrt(nodes / 16) / 16))))
+            nx = 16 * ny
+            p = slug_params(nx, ny, gamma=gamma, Re=Re, storage=storage)
+            edges = slug_edges(nx, np.random.default_rng(sub))
+            geo = dict(kind="bands", edges=edges, rho_band_r=float(gamma), rho_band_b=1.0)
+        out.append(dict(index=i, kind="bubble" if bubble else "slug", gamma=gamma, params=p, geo=geo,
+                        steps=steps, gap=gap, nodes=p["nx"] * p["ny"]))
+    return out
+
+
+def geo_fields(geo, nx, ny):
+    """Host colour-density fields of a ``serve_trace`` geometry."""
+    if geo["kind"] == "disk":
+        y, x = np.mgrid[0:ny, 0:nx]
+        inside = (x + 0.5 - geo["cx"]) ** 2 + (y + 0.5 - geo["cy"]) ** 2 < geo["radius"] ** 2
+        rr = np.where(inside, geo["rho_r_in"], geo["rho_r_out"])
+        rb = np.where(inside, geo["rho_b_in"], geo["rho_b_out"])
+        return rr.astype(np.float64), rb.astype(np.float64)
+    edges = list(geo["edges"]) + [nx]
+    red = np.zeros(nx, dtype=bool)
+    for b in range(len(edges) - 1):
+        red[edges[b]:edges[b + 1]] = (b % 2 == 0)
+    rr = np.where(red, geo["rho_band_r"], 0.0)[None, :] * np.ones((ny, 1))
+    rb = np.where(red, 0.0, geo["rho_band_b"])[None, :] * np.ones((ny, 1))
+    return rr.astype(np.float64), rb.astype(np.float64)

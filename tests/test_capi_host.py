@@ -54,7 +54,7 @@ def test_layout_sizes(lib):
     # 18 planes, pitch padded to 64
     assert lib.lbm_buffer_bytes(C.byref(cp)) == 18 * 128 * 10 * 4
     p16 = W.params(nx=100, ny=10, storage="f16s")
-    assert lib.lbm_buffer_bytes(C.byref(capi.make_params(p16))) == 18 * 128 * 10 * 2
+    assert lib.lbm_buffer_bytes(C.byref(capi.make_params(p16))) == 40 * 128 * 10   # FP32 rest + 8 x 16-bit
     assert _bytes(p) > 2 * 18 * 128 * 10 * 4
 
 

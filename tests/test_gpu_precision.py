@@ -1,0 +1,94 @@
+"""16-bit population storage against FP32 storage and the FP64 oracle:
+colour-mass conservation, spurious currents and the Laplace pressure jump of
+converged static bubbles (Sec. 4 static bubble tests; the 16-bit formats are
+this implementation's storage, not the paper's)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_01168_amd import capi
+from paper_1903_01168_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-precision]", *a, file=sys.stderr, flush=True)
+
+
+def _psi(rr, rb, p):
+    a, b = rr / p["rho0_r"], rb / p["rho0_b"]
+    return (a - b) / (a + b)
+
+
+def _laplace_fields(m, p, n):
+    """Pressure jump sampled at r < R - 4 and r > R + 4 around the lattice
+    centre, R the radius of a disk of the red area."""
+    R = math.sqrt((0.5 * (1 + _psi(m["rho_r"], m["rho_b"], p))).sum() / math.pi)
+    y, x = np.mgrid[0:n, 0:n]
+    r = np.hypot(x + 0.5 - n / 2, y + 0.5 - n / 2)
+    return m["p"][r < R - 4].mean() - m["p"][r > R + 4].mean(), R
+
+
+def _gpu(p, c, steps, storage):
+    q = dict(p, storage=storage)
+    with capi.Lattice(q) as g:
+        g.init(c["rho_r"], c["rho_b"])
+        g.step(steps)
+        d = g.diag(check=False)
+        R = math.sqrt(d["area_r"] / math.pi)
+        d = g.diag(circle=(p["nx"] / 2, p["ny"] / 2, R - 4, R + 4), check=False)
+    return d
+
+
+@pytest.fixture(scope="module")
+def c1_fp64():
+    c = W.static_bubble(n=64, radius=16)
+    s = oracle.Sim(**c["params"]).init(c["rho_r"], c["rho_b"], None, None)
+    s.step(20000)
+    dp, R = _laplace_fields(s.moments(), c["params"], 64)
+    say(f"C1 FP64 oracle: dp = {dp:.6e}, R = {R:.3f}, dp / (sigma/R) = {dp / (4e-3 / 9 / R):.5f}")
+    return c, dp
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_c1_laplace_against_fp64(c1_fp64, storage):
+    """Converged 64 x 64 static bubble (R = 16, A = 1e-3, 20000 steps): the
+    pressure jump of every storage format is within 1% of the FP64 oracle's."""
+    c, dp64 = c1_fp64
+    d = _gpu(c["params"], c, 20000, storage)
+    dp = d["p_in"] - d["p_out"]
+    mr, mb = c["rho_r"].sum(), c["rho_b"].sum()
+    say(f"C1 {storage}: dp rel. to FP64 {dp / dp64 - 1:+.2e}, mass drift {d['mass_r'] / mr - 1:+.1e} "
+        f"{d['mass_b'] / mb - 1:+.1e}, max|u| {d['max_u']:.2e}")
+    assert abs(dp / dp64 - 1) <= 0.01
+    assert abs(d["mass_r"] / mr - 1) <= 1e-7 and abs(d["mass_b"] / mb - 1) <= 1e-7
+    assert d["max_u"] <= 2e-5          # FP64: 5e-6
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_16bit_against_fp32(storage):
+    """Density-ratio bubbles and gravity slugs: 16-bit storage keeps colour
+    mass to FP32's level and spurious currents near FP32's."""
+    cases = []
+    for g in (10, 100):
+        cases.append((f"bubble 256 gamma={g}", W.bubble_cell(g, g, 64, n=256), 3000))
+    cases.append(("slug 512x32 gamma=10", W.gravity_slug(nx=512, ny=32, gamma=10, band_lo=60, band_hi=150), 3000))
+    for name, c, steps in cases:
+        p = c["params"]
+        out = {}
+        for st in ("f32", storage):
+            with capi.Lattice(dict(p, storage=st)) as g:
+                g.init(c["rho_r"], c["rho_b"])
+                g.step(steps)
+                out[st] = g.diag(check=False)
+        mr, mb = c["rho_r"].sum(), c["rho_b"].sum()
+        a, b = out["f32"], out[storage]
+        say(f"{name} {storage}: mass drift {b['mass_r'] / mr - 1:+.1e} {b['mass_b'] / mb - 1:+.1e} "
+            f"(f32 {a['mass_r'] / mr - 1:+.1e} {a['mass_b'] / mb - 1:+.1e}), max|u| {b['max_u']:.2e} (f32 {a['max_u']:.2e})")
+        assert b["n_nonfinite"] == 0
+        assert abs(b["mass_r"] / mr - 1) <= 1e-7 and abs(b["mass_b"] / mb - 1) <= 1e-7
+        assert b["max_u"] <= 1.5 * a["max_u"] + 1e-5

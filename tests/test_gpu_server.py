@@ -1,6 +1,7 @@
 """The solve server on the GPU: each request's result equals the same
 lattice stepped alone with lbm_step, bit for bit, whatever else ran in the
 same launches; a blowing-up request is isolated."""
+import math
 import sys
 
 import numpy as np
@@ -35,13 +36,17 @@ def _cases(storage):
     return cases
 
 
-def _alone(p, steps, rr, rb, color):
+def _alone(p, steps, rr, rb, color, init=None):
     with capi.Lattice(p) as g:
         g.init(rr, rb)
         if color is not None:
             g.set_inlet_color(color)
         g.step(steps)
-        return g.moments(check=False)
+        m = g.moments(check=False)
+        if init is not None and init["kind"] == serve.LBM_INIT_DISK:
+            R = math.sqrt(g.diag(check=False)["area_r"] / math.pi)
+            m["laplace"] = g.diag(circle=(init["cx"], init["cy"], R - 4.0, R + 4.0), check=False)
+        return m
 
 
 @pytest.mark.parametrize("storage,budget_lattices", [("f32", 100), ("f32", 2), ("f16s", 100)])
@@ -59,9 +64,13 @@ def test_served_equals_alone(storage, budget_lattices):
     assert st["peak_bytes"] <= budget
     for (p, init, steps, rr, rb, color), r in zip(cases, res):
         assert r["status"] == capi.LBM_OK and r["steps_done"] == steps
-        ref = _alone(p, steps, rr, rb, color)
+        ref = _alone(p, steps, rr, rb, color, init)
         for k in ("rho_r", "rho_b", "ux", "uy"):
             assert np.array_equal(r[k], ref[k]), (p["nx"], p["ny"], k)
+        if "laplace" in ref:    # Laplace sampling of a bubble request
+            for k in ("p_in", "p_out", "n_in", "n_out", "mass_r", "mass_b", "area_r"):
+                assert r["diag"][k] == ref["laplace"][k], (p["nx"], k)
+            assert r["diag"]["n_in"] > 0 and r["diag"]["n_out"] > 0
 
 
 def test_unstable_request_is_isolated():

@@ -61,3 +61,36 @@ def test_slug_bands_and_schedule():
     starts = [s for s, _ in sched]
     assert starts[0] == 0 and all(300 <= b - a <= 800 for a, b in zip(starts, starts[1:]))
     assert all(c1 == -c2 for (_, c1), (_, c2) in zip(sched, sched[1:]))
+
+
+def test_serve_trace_recipe():
+    a = W.serve_trace(seed=3, n=300)
+    b = W.serve_trace(seed=3, n=300)
+    assert [(r["kind"], r["nodes"], r["steps"], r["gamma"]) for r in a] == \
+        [(r["kind"], r["nodes"], r["steps"], r["gamma"]) for r in b]
+    kinds = {r["kind"] for r in a}
+    assert kinds == {"bubble", "slug"}
+    for r in a:
+        p = r["params"]
+        assert 64 * 64 // 4 <= r["nodes"] <= 1024 * 1024 and r["nodes"] == p["nx"] * p["ny"]
+        assert 1000 <= r["steps"] <= 50000 and r["gap"] > 0
+        assert r["gamma"] in W.SERVE_GAMMAS and p["storage"] == "f16s"
+        if r["kind"] == "bubble":
+            assert p["nx"] == p["ny"] and p["nx"] % 64 == 0 and p["bc_y"] == "periodic"
+            assert r["geo"]["radius"] == p["nx"] / 4 and p["rho0_b"] == r["gamma"]
+        else:
+            assert p["nx"] == 16 * p["ny"] and p["ny"] % 16 == 0 and p["bc_y"] == "walls"
+            e = r["geo"]["edges"]
+            assert e[0] == 0 and len(e) % 2 == 0 and all(x < y for x, y in zip(e, e[1:])) and e[-1] < p["nx"]
+
+
+def test_geo_fields_match_generators():
+    c = W.bubble_cell(100, 10, 30, n=128)
+    geo = dict(kind="disk", cx=64.0, cy=64.0, radius=30.0, rho_r_in=1.0, rho_b_in=0.0, rho_r_out=0.0,
+               rho_b_out=100.0)
+    rr, rb = W.geo_fields(geo, 128, 128)
+    assert np.array_equal(rr, c["rho_r"]) and np.array_equal(rb, c["rho_b"])
+    s = W.gravity_slug(seed=5, nx=1024, ny=32, gamma=10)
+    edges = W.slug_edges(1024, np.random.default_rng(5))
+    rr, rb = W.geo_fields(dict(kind="bands", edges=edges, rho_band_r=10.0, rho_band_b=1.0), 1024, 32)
+    assert np.array_equal(rr, s["rho_r"]) and np.array_equal(rb, s["rho_b"])
