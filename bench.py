@@ -172,17 +172,19 @@ def run_serve(args, log):
     lu = np.array([r["nodes"] * r["steps"] for r in trace], dtype=np.float64)
     budget = int(args.hbm_budget_gib * (1 << 30))
 
-    # capacity at moderate concurrency: a closed batch of the first requests
-    ncal = min(24, len(trace))
-    with serve.Server(budget, max_slots=4, chunk_steps=args.chunk, storage=args.storage) as s:
-        ids = [s.enqueue(r["params"], serve_init(r["geo"]), min(r["steps"], 2000)) for r in trace[:ncal]]
+    # capacity of the batched path: the first requests of the trace, all
+    # enqueued at once with the same step count (a saturated closed batch,
+    # admission and retirement included)
+    ncal = min(48, len(trace))
+    with serve.Server(budget, max_slots=args.max_slots, chunk_steps=args.chunk, storage=args.storage) as s:
+        ids = [s.enqueue(r["params"], serve_init(r["geo"]), 2000) for r in trace[:ncal]]
         res = [s.wait(i) for i in ids]
         st = s.stats()
     cal_span = max(r["t_done"] for r in res) - min(r["t_arrive"] for r in res)
     capacity = st["lattice_updates"] / cal_span / 1e6
     lam = args.load * capacity * 1e6 / lu.mean()            # requests per second
     arrive = np.cumsum([r["gap"] for r in trace]) / lam
-    log(f"serve: capacity {capacity:.0f} MLUPS at 4 concurrent, lambda {lam:.2f}/s, "
+    log(f"serve: capacity {capacity:.0f} MLUPS ({ncal} requests x 2000 steps at once), lambda {lam:.2f}/s, "
         f"trace span {arrive[-1]:.1f} s, {lu.sum():.3e} LU")
 
     # served run, arrivals in real time
@@ -242,7 +244,7 @@ def run_serve(args, log):
     serial_span = done - arrive[0]
 
     # Laplace jump and colour mass of the served 16-bit results against FP32
-    dpdiff, mdrift16, mdrift32, unstable16, unstable32 = [], [], [], 0, 0
+    dpdiff, dpsettled, mdrift16, mdrift32, unstable16, unstable32 = [], [], [], [], 0, 0
     for r, a, b, (m_r, m_b) in zip(trace, served, serial_diag, mass0):
         da = a["diag"]
         unstable16 += int(a["status"] != capi.LBM_OK)
@@ -255,6 +257,16 @@ def run_serve(args, log):
         x, y = dp_of(da, r), dp_of(b, r)
         if x is not None and y is not None:
             dpdiff.append(abs(x[0] - y[0]) / y[1])
+            if abs(y[0] / y[1] - 1.0) < 0.1:      # bubble has settled: FP32 within 10% of Laplace
+                dpsettled.append(abs(x[0] - y[0]) / y[1])
+    if args.records:
+        with open(args.records, "w") as fh:
+            for r, a, b, ls, l32 in zip(trace, served, serial_diag, lat, lat_serial):
+                x, y = dp_of(a["diag"], r), dp_of(b, r)
+                fh.write(json.dumps(dict(i=r["index"], kind=r["kind"], gamma=r["gamma"], nx=r["params"]["nx"],
+                                         ny=r["params"]["ny"], steps=r["steps"], status=a["status"],
+                                         lat=ls, lat_serial=l32, dp=x[0] if x else None,
+                                         dp32=y[0] if y else None, dpth=y[1] if y else None)) + "\n")
     bub = sum(1 for r in trace if r["kind"] == "bubble")
     return dict(
         value=lu.sum() / span / 1e6,
@@ -270,15 +282,21 @@ def run_serve(args, log):
             p50_s=pct(lat, 50), p99_s=pct(lat, 99), mean_s=float(np.mean(lat)), makespan_s=span,
             aggregate_mlups=lu.sum() / span / 1e6,
             busy_mlups=sst["lattice_updates"] / sst["busy_s"] / 1e6 if sst["busy_s"] else None,
-            busy_frac=sst["busy_s"] / span, chunks=sst["chunks"], peak_active=sst["peak_active"],
+            busy_frac=sst["busy_s"] / span, admit_s=sst["admit_s"], retire_s=sst["retire_s"],
+            chunks=sst["chunks"], peak_active=sst["peak_active"],
             peak_bytes=sst["peak_bytes"], unstable=unstable16, completed_ok=int(sum(ok)),
             serial_fp32=dict(p50_s=pct(lat_serial, 50), p99_s=pct(lat_serial, 99),
                              mean_s=float(np.mean(lat_serial)), makespan_s=serial_span,
                              aggregate_mlups=lu.sum() / serial_span / 1e6,
                              solve_mlups=lu.sum() / sum(service) / 1e6, unstable=unstable32),
+            # |dp(served, 16-bit) - dp(serial FP32)| / (sigma / R) per bubble request: all of
+            # them (many still in their pressure transient) and those that have settled
             laplace_dp_vs_fp32=dict(n=len(dpdiff), max=max(dpdiff) if dpdiff else None,
                                     p99=pct(dpdiff, 99), median=pct(dpdiff, 50),
-                                    over_1pct=int(sum(d > 0.01 for d in dpdiff))),
+                                    over_1pct=int(sum(d > 0.01 for d in dpdiff)),
+                                    settled_n=len(dpsettled), settled_max=max(dpsettled) if dpsettled else None,
+                                    settled_median=pct(dpsettled, 50),
+                                    settled_over_1pct=int(sum(d > 0.01 for d in dpsettled))),
             mass_drift=dict(served_max=max(mdrift16) if mdrift16 else None,
                             fp32_max=max(mdrift32) if mdrift32 else None),
         ),
@@ -350,6 +368,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=100, help="serve: steps per chunk")
     ap.add_argument("--max-slots", type=int, default=256, help="serve: lattices advanced together")
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0, help="serve: device memory budget")
+    ap.add_argument("--records", default="", help="serve: write one JSON line per request to this file")
     ap.add_argument("--copy-only", type=float, default=0.0,
                     help="only time the plain copy kernel over this many GiB (counter calibration)")
     args = ap.parse_args()

@@ -68,7 +68,9 @@ typedef struct {
     int64_t peak_active;
     uint64_t peak_bytes;        /* largest device memory held by active lattices             */
     double lattice_updates;     /* sum over finished work of nodes * steps                   */
-    double busy_s;              /* time spent running chunks                                  */
+    double busy_s;              /* time from chunk launch to chunk completion, summed         */
+    double admit_s;             /* host time spent admitting (allocation, set-up, init)       */
+    double retire_s;            /* host time spent retiring (diagnostics, fields, release)    */
 } lbm_server_stats;
 
 /* hbm_budget: device bytes the active lattices may hold in total (their

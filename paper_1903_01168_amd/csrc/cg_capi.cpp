@@ -179,14 +179,17 @@ static const int kWaveCols = 60;
 
 static int wave_tiles(int nx) { return (nx + kWaveCols - 1) / kWaveCols; }
 
-int plan_strip(int nx, int ny, int tx, int req)
+int plan_strip(long long nodes, int ny, int req)
 {
-    (void)tx;
     if (req > 0) return req < ny ? req : ny;
-    (void)nx;
-    // strips of 8 rows: 25% of the gathers are halo rows (served by L2) but the
-    // chip gets enough independent wavefronts; measured best from 512^2 to 8192^2
-    return ny < 8 ? ny : 8;
+    // A wavefront marches through its strip row by row, each row a dependent
+    // load -> collide -> store round trip (~1.5-2.5 us), so a launch takes at
+    // least strip x that.  Few nodes in the launch: short strips (latency);
+    // many: tall strips (fewer halo-row gathers, 2 per strip).  Thresholds
+    // from single-lattice sweeps of strip 1..16 at 64^2..2048^2; `nodes` is
+    // the node count of everything in the launch.
+    const int s = nodes <= (1LL << 17) ? 1 : nodes <= 1500000LL ? 2 : nodes <= 3000000LL ? 4 : 8;
+    return ny < s ? ny : s;
 }
 
 void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip)
@@ -224,7 +227,7 @@ static void drop_graphs(lbm_ctx *c)
 static int replan(lbm_ctx *c)
 {
     const int tx = c->tx ? c->tx : default_tx(c->p.nx, c->p.ny);
-    const int strip = plan_strip(c->p.nx, c->p.ny, tx, c->strip_req);
+    const int strip = plan_strip((long long)c->p.nx * c->p.ny, c->p.ny, c->strip_req);
     set_geometry(c->desc, &c->p, c->lay, tx, strip);
     c->desc.tile_begin = 0;
     c->desc.active_steps = INT_MAX;
@@ -682,11 +685,12 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
         for (int i = 0; i < n; ++i) tx = std::min(tx, default_tx(ctxs[i]->p.nx, ctxs[i]->p.ny));
     }
     b->tx = tx;
-    long long tiles = 0;
+    long long tiles = 0, nodes = 0;
+    for (int i = 0; i < n; ++i) nodes += (long long)ctxs[i]->p.nx * ctxs[i]->p.ny;
     for (int i = 0; i < n; ++i) {
         lbm_ctx *c = ctxs[i];
         SlotDesc d = c->desc;
-        set_geometry(d, &c->p, c->lay, tx, plan_strip(c->p.nx, c->p.ny, tx, c->strip_req));
+        set_geometry(d, &c->p, c->lay, tx, plan_strip(nodes, c->p.ny, c->strip_req));
         d.tile_begin = (int)tiles;
         d.active_steps = INT_MAX;
         if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer

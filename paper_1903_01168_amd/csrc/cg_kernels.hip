@@ -271,18 +271,39 @@ __global__ void __launch_bounds__(256) k_moments(const SlotDesc *__restrict__ sd
     }
 }
 
-__global__ void __launch_bounds__(64) k_reduce(const double *__restrict__ partial, int nblocks,
-                                               double *__restrict__ out)
+__global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ partial, int nblocks,
+                                                double *__restrict__ out)
 {
-    // one wave; lane j < 9 sums column j over the blocks in block order
-    const int j = threadIdx.x;
-    if (j >= 9) return;
-    double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        const double p = partial[(long long)b * 9 + j];
-        v = (j == 8) ? (p > v ? p : v) : v + p;
+    // thread t sums blocks t, t+256, ... in order; then a butterfly inside
+    // each wavefront (both lanes of a pair add the same two operands, so all
+    // lanes agree bit for bit) and the four wavefronts in order: a fixed
+    // association, independent of timing
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const double p = partial[(long long)b * 9 + j];
+            acc[j] = (j == 8) ? (p > acc[j] ? p : acc[j]) : acc[j] + p;
+        }
     }
-    out[j] = v;
+    __shared__ double red[4][9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        double v = acc[j];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(v, off, 64);
+            v = (j == 8) ? (o > v ? o : v) : v + o;
+        }
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int j = threadIdx.x;
+        double v = red[0][j];
+        for (int w = 1; w < 4; ++w) v = (j == 8) ? (red[w][j] > v ? red[w][j] : v) : v + red[w][j];
+        out[j] = v;
+    }
 }
 
 // ---------------------------------------------------- population access --
@@ -387,7 +408,7 @@ hipError_t launch_moments(int storage, const SlotDesc *d, long long nodes, int p
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, s, partial, g, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partial, g, out);
     return hipGetLastError();
 }
 

@@ -87,7 +87,10 @@ struct Backend {
     virtual ~Backend() = default;
     virtual size_t bytes(const lbm_params &p) = 0;
     virtual int admit(Request &r, std::string &err) = 0;
-    virtual int run_chunk(const std::vector<Request *> &act, int K, std::string &err) = 0;
+    // launch one chunk of K steps over `act` (asynchronous on the GPU)...
+    virtual int launch_chunk(const std::vector<Request *> &act, int K, std::string &err) = 0;
+    // ... and wait for it; then the step counts of `act` are advanced
+    virtual int wait_chunk(const std::vector<Request *> &act, int K, std::string &err) = 0;
     virtual void retire(Request &r) = 0;
     virtual double now() = 0;
 };
@@ -98,7 +101,8 @@ struct FakeBackend : Backend {
     explicit FakeBackend(double m) : mlups(m) {}
     size_t bytes(const lbm_params &p) override { return lbm_bytes_required(&p); }
     int admit(Request &, std::string &) override { return LBM_OK; }
-    int run_chunk(const std::vector<Request *> &act, int K, std::string &) override
+    int launch_chunk(const std::vector<Request *> &, int, std::string &) override { return LBM_OK; }
+    int wait_chunk(const std::vector<Request *> &act, int K, std::string &) override
     {
         double lu = 0.0;
         for (auto *r : act) {
@@ -180,15 +184,16 @@ struct GpuBackend : Backend {
         }
         return rc;
     }
-    int run_chunk(const std::vector<Request *> &act, int K, std::string &err) override
+    int launch_chunk(const std::vector<Request *> &act, int K, std::string &err) override
     {
         (void)hipSetDevice(device);
         table.clear();
-        long long tiles = 0;
+        long long tiles = 0, nodes = 0;
+        for (auto *r : act) nodes += r->nodes();
         for (auto *r : act) {
             lbm_ctx *c = r->ctx;
             cgd::SlotDesc d = c->desc;
-            cgi::set_geometry(d, &c->p, c->lay, tx, cgi::plan_strip(c->p.nx, c->p.ny, tx, 0));
+            cgi::set_geometry(d, &c->p, c->lay, tx, cgi::plan_strip(nodes, c->p.ny, 0));
             d.tile_begin = (int)tiles;
             d.active_steps = (int)std::min<int64_t>(K, r->steps - r->done);
             if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // launch 0 reads the current buffer
@@ -226,7 +231,15 @@ struct GpuBackend : Backend {
             }
         }
         if (e == hipSuccess) e = hipGraphLaunch(graph, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);   // the table is reused next chunk
+        if (e != hipSuccess) {
+            err = hipGetErrorString(e);
+            return LBM_E_DEVICE;
+        }
+        return LBM_OK;
+    }
+    int wait_chunk(const std::vector<Request *> &act, int K, std::string &err) override
+    {
+        const hipError_t e = hipStreamSynchronize(stream);   // the table is reused by the next chunk
         if (e != hipSuccess) {
             err = hipGetErrorString(e);
             return LBM_E_DEVICE;
@@ -297,72 +310,99 @@ struct lbm_server {
         cv_done.notify_all();
     }
 
+    // Admission: arrival order, the head of the queue waits for capacity.
+    // Called with the lock held; the backend's work runs unlocked.
+    void admit_pending(std::unique_lock<std::mutex> &lk)
+    {
+        while (!pending.empty() && (int)active.size() < max_slots && !stop) {
+            Request *r = pending.front();
+            if (r->bytes > budget) {
+                pending.pop_front();
+                finish(r, LBM_E_NOMEM);
+                continue;
+            }
+            if (held + r->bytes > budget) break;
+            pending.pop_front();
+            r->slot = free_slots.back();
+            free_slots.pop_back();
+            held += r->bytes;
+            lk.unlock();
+            std::string e;
+            const auto t = std::chrono::steady_clock::now();
+            const int rc = be->admit(*r, e);
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
+            lk.lock();
+            st.admit_s += dt;
+            if (rc != LBM_OK) {
+                held -= r->bytes;
+                free_slots.push_back(r->slot);
+                err = e;
+                finish(r, rc);
+                continue;
+            }
+            r->t_admit = be->now();
+            active.push_back(r);
+            st.admitted++;
+            st.peak_active = std::max<int64_t>(st.peak_active, (int64_t)active.size());
+            st.peak_bytes = std::max<uint64_t>(st.peak_bytes, held);
+        }
+    }
+
+    // One round: launch a chunk over the runnable lattices, admit arrivals
+    // while it runs on the device (their set-up is host work and device work
+    // queued behind the chunk), wait for the chunk, retire what finished.
     void loop()
     {
         std::unique_lock<std::mutex> lk(m);
         for (;;) {
             cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
             if (stop) break;
-            // admission: arrival order, the head of the queue waits for capacity
-            while (!pending.empty() && (int)active.size() < max_slots) {
-                Request *r = pending.front();
-                if (r->bytes > budget) {
-                    pending.pop_front();
-                    finish(r, LBM_E_NOMEM);
-                    continue;
-                }
-                if (held + r->bytes > budget) break;
-                pending.pop_front();
-                r->slot = free_slots.back();
-                free_slots.pop_back();
-                held += r->bytes;
-                lk.unlock();
-                std::string e;
-                const int rc = be->admit(*r, e);
-                lk.lock();
-                if (rc != LBM_OK) {
-                    held -= r->bytes;
-                    free_slots.push_back(r->slot);
-                    err = e;
-                    finish(r, rc);
-                    continue;
-                }
-                r->t_admit = be->now();
-                active.push_back(r);
-                st.admitted++;
-                st.peak_active = std::max<int64_t>(st.peak_active, (int64_t)active.size());
-                st.peak_bytes = std::max<uint64_t>(st.peak_bytes, held);
-            }
-            if (active.empty()) continue;
             std::vector<Request *> act;
             for (auto *r : active)
                 if (!r->fail_flag && r->done < r->steps) act.push_back(r);
             int rc = LBM_OK;
+            bool launched = false;
+            double t_launch = 0.0;
             if (!act.empty()) {
                 lk.unlock();
                 std::string e;
-                const double t = be->now();
-                rc = be->run_chunk(act, chunk, e);
-                const double dt = be->now() - t;
+                t_launch = be->now();
+                rc = be->launch_chunk(act, chunk, e);
+                lk.lock();
+                launched = rc == LBM_OK;
+                if (rc != LBM_OK) err = e;
+            }
+            admit_pending(lk);
+            if (launched) {
+                lk.unlock();
+                std::string e;
+                rc = be->wait_chunk(act, chunk, e);
+                const double dt = be->now() - t_launch;
                 lk.lock();
                 st.busy_s += dt;
                 st.chunks++;
                 st.launches += chunk;
                 if (rc != LBM_OK) err = e;
             }
-            // retire finished, failed and injected-failure lattices
+            // retire finished, failed and injected-failure lattices (a failed
+            // chunk fails the lattices that were in it)
             std::vector<Request *> keep;
             for (auto *r : active) {
+                const bool in_chunk = std::find(act.begin(), act.end(), r) != act.end();
                 const bool fin = r->done >= r->steps;
-                if (!fin && !r->fail_flag && rc == LBM_OK) {
+                const bool chunk_failed = rc != LBM_OK && in_chunk;
+                if (!fin && !r->fail_flag && !chunk_failed) {
                     keep.push_back(r);
                     continue;
                 }
                 if (r->fail_flag) r->status = LBM_E_UNSTABLE;
-                else if (rc != LBM_OK) r->status = rc;
+                else if (chunk_failed) r->status = rc;
                 lk.unlock();
+                const auto t = std::chrono::steady_clock::now();
                 be->retire(*r);
+                const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
                 lk.lock();
+                st.retire_s += dt;
                 st.lattice_updates += (double)r->nodes() * (double)r->done;
                 held -= r->bytes;
                 free_slots.push_back(r->slot);

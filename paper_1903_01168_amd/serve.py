@@ -43,6 +43,7 @@ class Stats(C.Structure):
         ("enqueued", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
         ("chunks", C.c_int64), ("launches", C.c_int64), ("peak_active", C.c_int64),
         ("peak_bytes", C.c_uint64), ("lattice_updates", C.c_double), ("busy_s", C.c_double),
+        ("admit_s", C.c_double), ("retire_s", C.c_double),
     ]
 
     def as_dict(self):

@@ -213,30 +213,33 @@ def random_fields(nx, ny, seed=0, rho0_r=1.0, rho0_b=1.0, umax=0.02, smooth=True
     return rho_r, rho_b, ux, uy
 
 
-SERVE_GAMMAS = (1, 10, 100, 1000)
+SERVE_GAMMAS = (1, 10, 100, 1000)     # bubbles
+SERVE_SLUG_GAMMAS = (1, 10)           # slugs (the gas-viscosity rule gives tau_g >> 10 beyond)
 
 
 def serve_trace(seed=0, n=2000, nodes_lo=64 * 64, nodes_hi=1024 * 1024, steps_lo=1000,
-                steps_hi=50000, M=10, Re=10, storage="f16s"):
+                steps_hi=50000, Re=10, storage="f16s"):
     """A seeded mix of solve requests: half static bubbles (square periodic
     lattice, side a multiple of 64, light disk of radius side/4 at the centre,
-    viscosity ratio M), half periodic gravity slugs (16:1 channel with walls,
-    height a multiple of 16, slugs 200..600 long, Reynolds number Re).  Node
-    counts and step counts are log-uniform in their ranges, the density ratio
-    is drawn from SERVE_GAMMAS, and ``gap`` is a unit-mean exponential
-    inter-arrival draw (divide by the arrival rate)."""
+    density ratio from SERVE_GAMMAS with the same kinematic viscosity in both
+    fluids, i.e. dynamic-viscosity ratio M = gamma), half periodic gravity
+    slugs (16:1 channel with walls, height a multiple of 16, slugs 200..600
+    long, Reynolds number Re, mu_g = mu_l / 2, density ratio from
+    SERVE_SLUG_GAMMAS).  Node counts and step counts are log-uniform in their
+    ranges, and ``gap`` is a unit-mean exponential inter-arrival draw (divide
+    by the arrival rate)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
         bubble = bool(rng.random() < 0.5)
         nodes = math.exp(rng.uniform(math.log(nodes_lo), math.log(nodes_hi)))
-        gamma = int(rng.choice(SERVE_GAMMAS))
+        gamma = int(rng.choice(SERVE_GAMMAS if bubble else SERVE_SLUG_GAMMAS))
         steps = int(round(math.exp(rng.uniform(math.log(steps_lo), math.log(steps_hi)))))
         gap = float(rng.exponential(1.0))
         sub = int(rng.integers(1 << 62))
         if bubble:
             side = int(min(1024, max(64, 64 * round(math.sqrt(nodes) / 64))))
-            p = bubble_params(gamma, M, n=side, storage=storage)
+            p = bubble_params(gamma, gamma, n=side, storage=storage)
             geo = dict(kind="disk", cx=side / 2, cy=side / 2, radius=side / 4, rho_r_in=1.0, rho_b_in=0.0,
                        rho_r_out=0.0, rho_b_out=float(gamma))
         else:

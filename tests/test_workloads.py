@@ -74,7 +74,8 @@ def test_serve_trace_recipe():
         p = r["params"]
         assert 64 * 64 // 4 <= r["nodes"] <= 1024 * 1024 and r["nodes"] == p["nx"] * p["ny"]
         assert 1000 <= r["steps"] <= 50000 and r["gap"] > 0
-        assert r["gamma"] in W.SERVE_GAMMAS and p["storage"] == "f16s"
+        assert r["gamma"] in (W.SERVE_GAMMAS if r["kind"] == "bubble" else W.SERVE_SLUG_GAMMAS)
+        assert p["storage"] == "f16s"
         if r["kind"] == "bubble":
             assert p["nx"] == p["ny"] and p["nx"] % 64 == 0 and p["bc_y"] == "periodic"
             assert r["geo"]["radius"] == p["nx"] / 4 and p["rho0_b"] == r["gamma"]
