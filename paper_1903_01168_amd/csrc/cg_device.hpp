@@ -111,7 +111,8 @@ template <> struct Codec<ST_F32> {
 //       direction's class at rest at the reference density of either fluid
 //       (equal for both fluids: the phases' alphas make rho0_k (1 - alpha_k)
 //       the same, Sec. 2.1.1).
-// Decoding: N_i = m_c + q 2^-12 max(rho0), N^r_i = g N_i, N^b_i = (1 - g) N_i.
+// Decoding: N_i = m_c + q 2^-12 max(rho0), N^r_i = g N_i, N^b_i = (1 - g) N_i
+// (one fused multiply-add from N_i).
 // The colour-blind population, which carries mass and momentum, is held as a
 // small deviation with FP16's relative precision in bulk and interface nodes
 // alike, and the colour split with a uniform 1.5e-5 quantum; a per-colour
@@ -137,9 +138,9 @@ __device__ __forceinline__ uint32_t mix32(uint32_t h)
     h ^= h >> 16;
     return h;
 }
-// next dither: linear congruential step (Numerical Recipes constants); its
-// high bits are the random ones
-__device__ __forceinline__ uint32_t lcg(uint32_t s) { return s * 1664525u + 1013904223u; }
+// j-th dither of a node: a Weyl sequence (golden-ratio increments) from the
+// node's hashed seed; its high bits are the ones used, and they spread evenly
+__device__ __forceinline__ uint32_t weyl(uint32_t seed, int j) { return seed + (uint32_t)j * 0x9e3779b9u; }
 
 typedef _Float16 cg_h2 __attribute__((ext_vector_type(2)));
 typedef __bf16 cg_b2 __attribute__((ext_vector_type(2)));
@@ -194,20 +195,24 @@ template <> struct Codec<ST_BF16S> {
     }
 };
 
-// red share of a stored pair: u / 65535 (to within 2e-10; exactly 0 and 1 at
-// the ends), and the blue share from 65535 - u in the same way
-__device__ __forceinline__ float share(uint32_t u)
+// red share of a stored pair: u / 65535 to within 3e-8, exactly 0 and 1 at
+// the ends, monotone in u
+__device__ __forceinline__ float share(uint32_t u) { return (float)u * (1.f / 65535.f); }
+// The colour split of a decoded colour-blind population.  Encoder and decoder
+// must produce the same bits, so every rounding is spelled out (an explicit
+// fma: left to the compiler, N - g N may or may not be contracted depending
+// on the surrounding code).  Exactly N / 0 at u = 65535 and 0 / N at u = 0.
+__device__ __forceinline__ void split(float N, uint32_t u, float &nr, float &nb)
 {
-    const float f = (float)u;
-    return __builtin_fmaf(f, 0x1p-32f, f * 0x1p-16f);
+    const float g = share(u);
+    nr = g * N;
+    nb = __builtin_fmaf(-g, N, N);
 }
 template <int ST>
 __device__ __forceinline__ void dec_pair(const SlotDesc &S, int c, uint16_t q, uint16_t u, float &N, float &nr, float &nb)
 {
-    const float gr = share(u), gb = share(65535u - u);
     N = __builtin_fmaf(Codec<ST>::dec_q(q), S.dmul, S.mref[c]);
-    nr = gr * N;
-    nb = gb * N;
+    split(N, u, nr, nb);
 }
 
 // Encode a pair; returns the decoded values the store leaves behind.
@@ -221,15 +226,13 @@ __device__ __forceinline__ void enc_pair(const SlotDesc &S, int c, float vr, flo
     float g = vr * __builtin_amdgcn_rcpf(n);
     g = g > 0.f ? (g < 1.f ? g : 1.f) : 0.f;          // NaN -> 0 (its N stays NaN)
     g = vb == 0.f ? 1.f : (vr == 0.f ? 0.f : g);       // an absent colour stays exactly absent
-    const float dith = sr ? (float)(rg >> 16) * 0x1p-16f : 0.5f;
+    // dither in [0, 1) from the top 23 bits (as the mantissa of a number in [1, 2))
+    const float dith = sr ? __uint_as_float(0x3f800000u | (rg >> 9)) - 1.f : 0.5f;
     const uint32_t ui = (uint32_t)__builtin_fmaf(g, 65535.f, dith);   // g in [0,1]: 0 .. 65535
     u = (uint16_t)(ui > 65535u ? 65535u : ui);
-    const float gr = share(u), gb = share(65535u - u);
     const float x = (n - S.mref[c]) * S.dscale;
     q = sr ? Codec<ST>::enc_q(x, rq) : Codec<ST>::enc_q_nearest(x);
-    const float N = __builtin_fmaf(Codec<ST>::dec_q(q), S.dmul, S.mref[c]);
-    nr = gr * N;
-    nb = gb * N;
+    split(__builtin_fmaf(Codec<ST>::dec_q(q), S.dmul, S.mref[c]), u, nr, nb);
 }
 
 // FP32 rest population of a colour: the value itself or its deviation from
@@ -531,21 +534,22 @@ __device__ __forceinline__ void store18(const SlotDesc &S, const Halves &h, uint
             C::store(outb[i], h.r[1], voff, (uint32_t)i * pb + rowoff, S, 1, vclass(i));
         }
     } else {
-        uint32_t rnd = mix32((voff + rowoff) ^ mix32(__float_as_uint(outr[1]) ^ __float_as_uint(outb[5]) * 0x9e3779b9u));
+        // one seed per node from its position and two of the values stored
+        const uint32_t seed = mix32((voff + rowoff) ^ __float_as_uint(outr[1]) ^
+                                    __builtin_rotateleft32(__float_as_uint(outb[5]), 13));
         double ar = 0.0, ab = 0.0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const uint32_t rg = lcg(rnd);
-            rnd = lcg(rg);
             uint16_t q, u;
             float nr, nb;
-            enc_pair<ST>(S, vclass(i), outr[i], outb[i], rg, rnd, CG_CODEC_SR != 0, q, u, nr, nb);
+            enc_pair<ST>(S, vclass(i), outr[i], outb[i], weyl(seed, 2 * i), weyl(seed, 2 * i + 1), CG_CODEC_SR != 0,
+                         q, u, nr, nb);
             ar += (double)nr;
             ab += (double)nb;
             C::put(q, h.r[0], voff, plane_off<ST>(i, pb) + rowoff);
             C::put(u, h.r[1], voff, plane_off<ST>(i, pb) + rowoff);
         }
-        const uint32_t r1 = lcg(rnd), r2 = lcg(r1);
+        const uint32_t r1 = weyl(seed, 18), r2 = weyl(seed, 19);
         const double d1 = CG_CODEC_SR ? (double)(r1 >> 8) * 0x1p-24 : 0.5, d2 = CG_CODEC_SR ? (double)(r2 >> 8) * 0x1p-24 : 0.5;
         __builtin_amdgcn_raw_buffer_store_b32(enc_rest(mr - ar, S.rest0[0], d1), h.r[0], (int)(2u * voff), (int)(2u * rowoff),
                                               CG_STORE_POLICY);
