@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
+# the kernels and the host planner that picks their launch shape
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_01168_amd", "csrc", f)
-                  for f in ("cg_device.hpp", "cg_kernels.hip")]
+                  for f in ("cg_device.hpp", "cg_kernels.hip", "cg_capi.cpp")]
 
 
 def kernel_hash():

@@ -179,16 +179,23 @@ static const int kWaveCols = 60;
 
 static int wave_tiles(int nx) { return (nx + kWaveCols - 1) / kWaveCols; }
 
-int plan_strip(long long nodes, int ny, int req)
+int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req)
 {
     if (req > 0) return req < ny ? req : ny;
     // A wavefront marches through its strip row by row, each row a dependent
     // load -> collide -> store round trip (~1.5-2.5 us), so a launch takes at
     // least strip x that.  Few nodes in the launch: short strips (latency);
-    // many: tall strips (fewer halo-row gathers, 2 per strip).  Thresholds
-    // from single-lattice sweeps of strip 1..16 at 64^2..2048^2; `nodes` is
-    // the node count of everything in the launch.
-    const int s = nodes <= (1LL << 17) ? 1 : nodes <= 1500000LL ? 2 : nodes <= 3000000LL ? 4 : 8;
+    // many: taller strips (fewer halo-row gathers, 2 per strip).  `nodes` is
+    // the node count of everything in the launch.  Thresholds measured with
+    // strips of 1..16 rows on 64^2..8192^2 bubbles, a 4096 x 256 slug, an
+    // 8192 x 512 channel and the nine-lattice 512^2 sweep: FP32 runs best with
+    // 4-row strips on wide lattices and 8 on narrow ones (512 columns, 9
+    // wavefront tiles), 16-bit storage with 4 rows up to 3M nodes and 8 beyond.
+    int s;
+    if (nodes <= (1LL << 17)) s = 1;
+    else if (nodes <= 1500000LL) s = 2;
+    else if (storage == LBM_STORE_F32) s = tiles_x >= 16 ? 4 : 8;
+    else s = nodes <= 3000000LL ? 4 : 8;
     return ny < s ? ny : s;
 }
 
@@ -227,7 +234,8 @@ static void drop_graphs(lbm_ctx *c)
 static int replan(lbm_ctx *c)
 {
     const int tx = c->tx ? c->tx : default_tx(c->p.nx, c->p.ny);
-    const int strip = plan_strip((long long)c->p.nx * c->p.ny, c->p.ny, c->strip_req);
+    set_geometry(c->desc, &c->p, c->lay, tx, 1);   // tiles_x does not depend on the strip
+    const int strip = plan_strip((long long)c->p.nx * c->p.ny, c->p.ny, c->desc.tiles_x, c->p.storage, c->strip_req);
     set_geometry(c->desc, &c->p, c->lay, tx, strip);
     c->desc.tile_begin = 0;
     c->desc.active_steps = INT_MAX;
@@ -690,7 +698,8 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
     for (int i = 0; i < n; ++i) {
         lbm_ctx *c = ctxs[i];
         SlotDesc d = c->desc;
-        set_geometry(d, &c->p, c->lay, tx, plan_strip(nodes, c->p.ny, c->strip_req));
+        set_geometry(d, &c->p, c->lay, tx, 1);
+        set_geometry(d, &c->p, c->lay, tx, plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, c->strip_req));
         d.tile_begin = (int)tiles;
         d.active_steps = INT_MAX;
         if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer

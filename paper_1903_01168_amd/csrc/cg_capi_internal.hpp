@@ -53,7 +53,7 @@ int validate(const lbm_params *p, std::string &msg);
 Layout layout(const lbm_params *p);
 void fill_desc(const lbm_params *p, cgd::SlotDesc &d);
 int default_tx(int nx, int ny);
-int plan_strip(long long nodes, int ny, int req);
+int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req);
 void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip);
 
 }  // namespace cgi

@@ -193,7 +193,8 @@ struct GpuBackend : Backend {
         for (auto *r : act) {
             lbm_ctx *c = r->ctx;
             cgd::SlotDesc d = c->desc;
-            cgi::set_geometry(d, &c->p, c->lay, tx, cgi::plan_strip(nodes, c->p.ny, 0));
+            cgi::set_geometry(d, &c->p, c->lay, tx, 1);
+            cgi::set_geometry(d, &c->p, c->lay, tx, cgi::plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, 0));
             d.tile_begin = (int)tiles;
             d.active_steps = (int)std::min<int64_t>(K, r->steps - r->done);
             if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // launch 0 reads the current buffer
