@@ -55,7 +55,7 @@ def build_cells(args, W):
         return [c], "gravity slug 4096x256"
     if args.workload == "channel":
         c = W.inlet_outlet(seed=args.seed, storage=args.storage, collision=args.collision)
-        return [c], "inlet/outlet channel 8192x512"
+        return [c], "inlet/outlet channel 8192x512 (stratified inflow, density ratio 5)"
     if args.workload == "hbm8192":
         c = W.static_bubble(n=8192, radius=2048.0, storage=args.storage, collision=args.collision)
         return [c], "static bubble 8192x8192"
@@ -425,7 +425,9 @@ def main():
         if args.strip or args.tile:
             lat.set_launch(args.tile, args.strip)
         lat.init(c["rho_r"], c["rho_b"], c["ux"], c["uy"])
-        if "schedule" in c:
+        if "inlet_color" in c:
+            lat.set_inlet_color(c["inlet_color"])
+        elif "schedule" in c:
             lat.set_inlet_color(np.full(c["params"]["ny"], c["schedule"][0][1], dtype=np.int8))
         lats.append(lat)
     mass0 = [lat.diag(check=False) for lat in lats]

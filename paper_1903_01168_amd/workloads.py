@@ -177,24 +177,36 @@ def inlet_schedule(total_steps, seed=0, lo=300, hi=800, first_red=True):
     return seg
 
 
-def inlet_outlet(seed=0, nx=8192, ny=512, gamma=100, M=10, u_in=0.01, A=1e-3, beta=0.7,
-                 tau_heavy=0.6, storage="f32", collision="bgk", total_steps=200000):
-    """Channel: west velocity inlet, east pressure outlet, walls top/bottom.
-    Heavy fluid red (rho0_r = gamma), light blue.  nu_heavy/nu_light = M/gamma;
-    tau_heavy = 0.6.  Initial fill: light fluid at rest.  The outlet pressure
-    is the common reference pressure of the two fluids, written here as the
-    light fluid's rho0 times its squared sound speed 3 (1 - alpha_light) / 5."""
+def inlet_outlet(seed=0, nx=8192, ny=512, gamma=5, u_in=0.01, A=1e-3, beta=0.7, tau_heavy=0.6,
+                 gas_fraction=0.2, storage="f32", collision="bgk", alternating=False, M=None,
+                 total_steps=200000):
+    """Channel with a west velocity inlet, an east pressure outlet and walls
+    top/bottom, set up as the paper's open-channel case (Sec. 5.2): heavy
+    liquid (red, rho0_r = gamma) below light gas (blue), volume fractions
+    0.8 / 0.2 in the initial fill and in the inflow, which enters with u_in in
+    both phases; mu_g = mu_l / 2 (or nu_heavy / nu_light = M / gamma when M is
+    given); tau_heavy = 0.6.  The outlet pressure is the common reference
+    pressure, the light fluid's rho0 times 3 (1 - alpha_light) / 5.
+    ``alternating``: instead, a channel filled with gas into which whole
+    columns of liquid and gas are injected in turns on a seeded 300..800-step
+    schedule (``schedule``)."""
     nu_h = nu_from_tau(tau_heavy)
-    nu_l = nu_h * gamma / M
+    nu_l = nu_h * gamma / 2.0 if M is None else nu_h * gamma / M
     p0 = 0.48   # rho0_light * 3 (1 - 0.2) / 5
     p = params(nx=nx, ny=ny, bc_x="open", bc_y="walls", rho0_r=float(gamma), rho0_b=1.0,
                tau_r=tau_heavy, tau_b=tau_from_nu(nu_l), A=A, beta=beta, u_in_r=u_in,
                u_in_b=u_in, p_out=p0, storage=storage, collision=collision)
-    rr = np.zeros((ny, nx))
-    rb = np.ones((ny, nx))
-    return dict(name=f"inlet-outlet {nx}x{ny} gamma={gamma} M={M}", params=p, rho_r=rr,
-                rho_b=rb, ux=None, uy=None,
-                schedule=inlet_schedule(total_steps, seed=seed))
+    visc = "mu_g=mu_l/2" if M is None else f"M={M}"
+    if alternating:
+        return dict(name=f"inlet-outlet {nx}x{ny} gamma={gamma} {visc} alternating", params=p,
+                    rho_r=np.zeros((ny, nx)), rho_b=np.ones((ny, nx)), ux=None, uy=None,
+                    schedule=inlet_schedule(total_steps, seed=seed))
+    heavy = np.arange(ny) < int(round((1.0 - gas_fraction) * ny))
+    rr = np.where(heavy[:, None], float(gamma), 0.0) * np.ones((1, nx))
+    rb = np.where(heavy[:, None], 0.0, 1.0) * np.ones((1, nx))
+    return dict(name=f"inlet-outlet {nx}x{ny} gamma={gamma} {visc} stratified", params=p,
+                rho_r=rr, rho_b=rb, ux=None, uy=None,
+                inlet_color=np.where(heavy, 1, -1).astype(np.int8))
 
 
 def random_fields(nx, ny, seed=0, rho0_r=1.0, rho0_b=1.0, umax=0.02, smooth=True):
