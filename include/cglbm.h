@@ -153,16 +153,24 @@ void *lbm_stream(const lbm_ctx *ctx);
 /* ---- batched stepping -------------------------------------------------
  * A batch advances several contexts (same device, same storage type) with ONE
  * kernel launch per time step: every workgroup finds its lattice in a device
- * table of lattice descriptors.  Each lattice's arithmetic is exactly that of
- * lbm_step, so results are bit-identical to stepping the contexts one by one.
- * The contexts must not be stepped outside the batch while it exists
- * (LBM_E_INVAL otherwise); lbm_moments / lbm_diag / checkpoints on them stay
- * valid.  tile_x: 0 (automatic), 64, 128 or 256. */
+ * table of lattice descriptors.  When the contexts' buffers together exceed
+ * the last-level cache budget (192 MiB of MI355X's 256 MB Infinity Cache) the
+ * batch is split into groups that fit, balanced by bytes, and lbm_batch_step
+ * advances the groups in turns of 256 steps (each group one launch per step);
+ * after the call every context has advanced n steps.  Each lattice's
+ * arithmetic is exactly that of lbm_step, so results are bit-identical to
+ * stepping the contexts one by one, in any grouping.  The contexts must not
+ * be stepped outside the batch while it exists (LBM_E_INVAL otherwise);
+ * lbm_moments / lbm_diag / checkpoints on them stay valid.  tile_x: 0
+ * (automatic), 64, 128 or 256. */
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_stream, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t n);
 int lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
+/* Number of cache-sized groups of the batch, i.e. kernel launches per step
+ * (0 for a NULL batch). */
+int lbm_batch_groups(const lbm_batch *b);
 
 /* Plain device-to-device copy of n bytes on the context stream (measures
  * achievable HBM bandwidth beside the step). */

@@ -56,7 +56,7 @@ EXPORTS = [
     "lbm_create_ext", "lbm_destroy", "lbm_init_fields", "lbm_set_inlet_color", "lbm_step",
     "lbm_steps_done", "lbm_sync", "lbm_moments", "lbm_diag", "lbm_get_pops", "lbm_set_pops",
     "lbm_save_state", "lbm_load_state", "lbm_set_launch", "lbm_stream", "lbm_bw_copy",
-    "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error",
+    "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_groups",
 ]
 
 _LIB = None
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     L.lbm_batch_destroy.argtypes = [_P]
     L.lbm_batch_last_error.restype = C.c_char_p
     L.lbm_batch_last_error.argtypes = [_P]
+    L.lbm_batch_groups.argtypes = [_P]
     _LIB = L
     return L
 
@@ -268,6 +269,11 @@ class Batch:
         if rc != LBM_OK:
             raise LbmError(rc, self.L.lbm_last_error(None).decode())
         self._h = h
+
+    @property
+    def groups(self) -> int:
+        """Cache-sized groups, i.e. kernel launches per step."""
+        return int(self.L.lbm_batch_groups(self._h))
 
     def step(self, n=1):
         rc = self.L.lbm_batch_step(self._h, int(n))

@@ -199,6 +199,26 @@ int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req)
     return ny < s ? ny : s;
 }
 
+std::vector<int> cache_groups(const std::vector<size_t> &bytes)
+{
+    const int n = (int)bytes.size();
+    size_t total = 0;
+    for (size_t b : bytes) total += b;
+    const int ng = (int)std::min<size_t>((size_t)std::max(n, 1),
+                                         std::max<size_t>(1, (total + kCacheBudget - 1) / kCacheBudget));
+    std::vector<int> first(1, 0);
+    size_t acc = 0;
+    for (int i = 0, g = 1; i + 1 < n && g < ng; ++i) {
+        acc += bytes[i];
+        if (acc * ng >= total * g) {   // the groups so far hold their share
+            first.push_back(i + 1);
+            ++g;
+        }
+    }
+    first.push_back(n);
+    return first;
+}
+
 void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip)
 {
     d.nx = p->nx;
@@ -633,16 +653,24 @@ int lbm_bw_copy(lbm_ctx *c, void *dst, const void *src, size_t n)
 }  // extern "C"
 
 // ------------------------------------------------------------------ batch --
+// Steps per turn of a batch's cache groups (a multiple of kGraphSteps).
+static const int64_t kRoundSteps = 256;
+
+struct BatchGroup {
+    std::vector<SlotDesc> slots;
+    SlotDesc *d_slots = nullptr;
+    int tiles = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
 struct lbm_batch {
     std::vector<lbm_ctx *> ctx;
     std::vector<int64_t> base;          // ctx step counter at creation
-    std::vector<SlotDesc> slots;
-    SlotDesc *d_slots = nullptr;
+    std::vector<BatchGroup> groups;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    int device = 0, storage = 0, tx = 0, tiles = 0;
+    int device = 0, storage = 0, tx = 0;
     int64_t steps = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err;
 };
 
@@ -661,9 +689,11 @@ int lbm_batch_destroy(lbm_batch *b)
     if (!b) return LBM_OK;
     DeviceGuard g(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    for (auto &x : b->graph)
-        if (x) (void)hipGraphExecDestroy(x);
-    if (b->d_slots) (void)hipFree(b->d_slots);
+    for (auto &G : b->groups) {
+        for (auto &x : G.graph)
+            if (x) (void)hipGraphExecDestroy(x);
+        if (G.d_slots) (void)hipFree(G.d_slots);
+    }
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return LBM_OK;
@@ -693,68 +723,109 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
         for (int i = 0; i < n; ++i) tx = std::min(tx, default_tx(ctxs[i]->p.nx, ctxs[i]->p.ny));
     }
     b->tx = tx;
-    long long tiles = 0, nodes = 0;
-    for (int i = 0; i < n; ++i) nodes += (long long)ctxs[i]->p.nx * ctxs[i]->p.ny;
+    std::vector<size_t> bytes;
+    for (int i = 0; i < n; ++i) bytes.push_back(2 * ctxs[i]->buf_bytes);
+    const std::vector<int> first = cache_groups(bytes);
+    b->groups.resize(first.size() - 1);
+    for (size_t gi = 0; gi + 1 < first.size(); ++gi) {
+        BatchGroup &G = b->groups[gi];
+        long long tiles = 0, nodes = 0;
+        for (int i = first[gi]; i < first[gi + 1]; ++i) nodes += (long long)ctxs[i]->p.nx * ctxs[i]->p.ny;
+        for (int i = first[gi]; i < first[gi + 1]; ++i) {
+            lbm_ctx *c = ctxs[i];
+            SlotDesc d = c->desc;
+            set_geometry(d, &c->p, c->lay, tx, 1);
+            set_geometry(d, &c->p, c->lay, tx, plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, c->strip_req));
+            d.tile_begin = (int)tiles;
+            d.active_steps = INT_MAX;
+            if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer
+            tiles += (long long)d.tiles_x * d.tiles_y;
+            G.slots.push_back(d);
+        }
+        if (tiles > INT_MAX / 2) {
+            lbm_batch_destroy(b);
+            return fail(nullptr, LBM_E_INVAL, "batch too large");
+        }
+        G.tiles = (int)tiles;
+    }
     for (int i = 0; i < n; ++i) {
-        lbm_ctx *c = ctxs[i];
-        SlotDesc d = c->desc;
-        set_geometry(d, &c->p, c->lay, tx, 1);
-        set_geometry(d, &c->p, c->lay, tx, plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, c->strip_req));
-        d.tile_begin = (int)tiles;
-        d.active_steps = INT_MAX;
-        if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer
-        tiles += (long long)d.tiles_x * d.tiles_y;
-        b->slots.push_back(d);
-        b->ctx.push_back(c);
-        b->base.push_back(c->steps);
+        b->ctx.push_back(ctxs[i]);
+        b->base.push_back(ctxs[i]->steps);
     }
-    if (tiles > INT_MAX / 2) {
-        lbm_batch_destroy(b);
-        return fail(nullptr, LBM_E_INVAL, "batch too large");
-    }
-    b->tiles = (int)tiles;
     hipError_t e;
     if (hip_stream) b->stream = (hipStream_t)hip_stream;
     else b->stream = ctxs[0]->stream;
-    if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipMalloc(&b->d_slots, b->slots.size() * sizeof(SlotDesc))) != hipSuccess) {
-        b->d_slots = nullptr;
+    if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
         lbm_batch_destroy(b);
         return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
     }
+    for (auto &G : b->groups)
+        if ((e = hipMalloc(&G.d_slots, G.slots.size() * sizeof(SlotDesc))) != hipSuccess) {
+            G.d_slots = nullptr;
+            lbm_batch_destroy(b);
+            return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+        }
     // the contexts' pending work must finish before the batch stream uses their buffers
     for (auto *c : b->ctx) (void)hipStreamSynchronize(c->stream);
-    e = hipMemcpy(b->d_slots, b->slots.data(), b->slots.size() * sizeof(SlotDesc), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        lbm_batch_destroy(b);
-        return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+    for (auto &G : b->groups) {
+        e = hipMemcpy(G.d_slots, G.slots.data(), G.slots.size() * sizeof(SlotDesc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            lbm_batch_destroy(b);
+            return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+        }
     }
     *out = b;
     return LBM_OK;
 }
 
-static int batch_graph(lbm_batch *b, int parity)
+static int batch_graph(lbm_batch *b, BatchGroup &G, int parity)
 {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
     hipError_t le = hipSuccess;
     for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
-        le = cgd::launch_step(b->storage, b->tx, b->d_slots, (int)b->slots.size(), b->tiles, (parity + j) & 1, 0,
+        le = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (parity + j) & 1, 0,
                               b->cap_stream);
     e = hipStreamEndCapture(b->cap_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
         return bfail(b, LBM_E_DEVICE, std::string("capture: ") + hipGetErrorString(le != hipSuccess ? le : e));
     }
-    e = hipGraphInstantiate(&b->graph[parity], graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&G.graph[parity], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        b->graph[parity] = nullptr;
+        G.graph[parity] = nullptr;
         return bfail(b, LBM_E_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
     }
     return LBM_OK;
 }
+
+// n steps of one group, starting at batch step `start` (graph replays, then
+// single launches)
+static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n)
+{
+    int64_t t = start;
+    while (n >= 2 * kGraphSteps || (n >= kGraphSteps && n % kGraphSteps == 0)) {
+        const int par = (int)(t & 1);
+        if (!G.graph[par]) {
+            int rc = batch_graph(b, G, par);
+            if (rc != LBM_OK) return rc;
+        }
+        hipError_t e = hipGraphLaunch(G.graph[par], b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+        t += kGraphSteps;
+        n -= kGraphSteps;
+    }
+    for (; n > 0; --n, ++t) {
+        hipError_t e = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (int)(t & 1), 0,
+                                        b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_groups(const lbm_batch *b) { return b ? (int)b->groups.size() : 0; }
 
 int lbm_batch_step(lbm_batch *b, int64_t n)
 {
@@ -764,26 +835,17 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
         if (b->ctx[i]->steps - b->base[i] != b->steps)
             return bfail(b, LBM_E_INVAL, "a context of the batch was stepped outside it");
     DeviceGuard g(b->device);
-    auto advance = [&](int64_t k) {
-        b->steps += k;
-        for (auto *c : b->ctx) c->steps += k;
-    };
-    while (n >= 2 * kGraphSteps) {
-        const int par = (int)(b->steps & 1);
-        if (!b->graph[par]) {
-            int rc = batch_graph(b, par);
+    // one group: all steps at once; several: rounds of kRoundSteps per group
+    const int64_t round = b->groups.size() == 1 ? n : kRoundSteps;
+    while (n > 0) {
+        const int64_t k = std::min(n, round);
+        for (auto &G : b->groups) {
+            const int rc = group_steps(b, G, b->steps, k);
             if (rc != LBM_OK) return rc;
         }
-        hipError_t e = hipGraphLaunch(b->graph[par], b->stream);
-        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
-        advance(kGraphSteps);
-        n -= kGraphSteps;
-    }
-    for (; n > 0; --n) {
-        hipError_t e = cgd::launch_step(b->storage, b->tx, b->d_slots, (int)b->slots.size(), b->tiles,
-                                        (int)(b->steps & 1), 0, b->stream);
-        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
-        advance(1);
+        b->steps += k;
+        for (auto *c : b->ctx) c->steps += k;
+        n -= k;
     }
     return LBM_OK;
 }

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "cg_device.hpp"
 #include "cglbm.h"
@@ -54,6 +55,15 @@ Layout layout(const lbm_params *p);
 void fill_desc(const lbm_params *p, cgd::SlotDesc &d);
 int default_tx(int nx, int ny);
 int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req);
+
+// Lattices stepped together whose buffers exceed the last-level cache are
+// split into contiguous groups that fit (MI355X: 256 MB Infinity Cache) and
+// the groups take turns: a group's populations then stay cache-resident from
+// one step to the next.  Lattices are independent, so results do not change.
+constexpr size_t kCacheBudget = 192ull << 20;
+// First index of each group (plus the end), balanced by bytes; `bytes` holds
+// the device bytes that each lattice's steps touch (its two buffers).
+std::vector<int> cache_groups(const std::vector<size_t> &bytes);
 void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip);
 
 }  // namespace cgi

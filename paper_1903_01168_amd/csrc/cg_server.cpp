@@ -128,15 +128,20 @@ struct GpuBackend : Backend {
     bool own_stream = false;
     cgd::SlotDesc *d_slots = nullptr;
     std::vector<cgd::SlotDesc> table;
-    hipGraphExec_t graph = nullptr;
-    int g_nslots = -1, g_tiles = -1, g_K = -1;
+    // one captured chunk per cache group, re-captured when its shape changes
+    struct Chunk {
+        hipGraphExec_t graph = nullptr;
+        int off = -1, nslots = -1, tiles = -1, K = -1;
+    };
+    std::vector<Chunk> chunks;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     GpuBackend(int st, int t, int ms) : storage(st), tx(t), max_slots(ms) {}
     ~GpuBackend() override
     {
         if (stream) (void)hipStreamSynchronize(stream);
-        if (graph) (void)hipGraphExecDestroy(graph);
+        for (auto &c : chunks)
+            if (c.graph) (void)hipGraphExecDestroy(c.graph);
         if (d_slots) (void)hipFree(d_slots);
         if (cap) (void)hipStreamDestroy(cap);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -184,54 +189,61 @@ struct GpuBackend : Backend {
         }
         return rc;
     }
+    // Chunk of K steps over the active lattices: cache-sized groups (in
+    // admission order) run their K launches in turn, each from its own graph.
     int launch_chunk(const std::vector<Request *> &act, int K, std::string &err) override
     {
         (void)hipSetDevice(device);
         table.clear();
-        long long tiles = 0, nodes = 0;
-        for (auto *r : act) nodes += r->nodes();
-        for (auto *r : act) {
-            lbm_ctx *c = r->ctx;
-            cgd::SlotDesc d = c->desc;
-            cgi::set_geometry(d, &c->p, c->lay, tx, 1);
-            cgi::set_geometry(d, &c->p, c->lay, tx, cgi::plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, 0));
-            d.tile_begin = (int)tiles;
-            d.active_steps = (int)std::min<int64_t>(K, r->steps - r->done);
-            if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // launch 0 reads the current buffer
-            tiles += (long long)d.tiles_x * d.tiles_y;
-            table.push_back(d);
-        }
-        if (tiles > INT_MAX / 2) {
-            err = "too many tiles in one chunk";
-            return LBM_E_INVAL;
+        std::vector<size_t> bytes;
+        for (auto *r : act) bytes.push_back(2 * r->ctx->buf_bytes);
+        const std::vector<int> first = cgi::cache_groups(bytes);
+        const int ng = (int)first.size() - 1;
+        std::vector<int> gtiles(ng, 0);
+        for (int g = 0; g < ng; ++g) {
+            long long tiles = 0, nodes = 0;
+            for (int i = first[g]; i < first[g + 1]; ++i) nodes += act[i]->nodes();
+            for (int i = first[g]; i < first[g + 1]; ++i) {
+                const Request *r = act[i];
+                lbm_ctx *c = r->ctx;
+                cgd::SlotDesc d = c->desc;
+                cgi::set_geometry(d, &c->p, c->lay, tx, 1);
+                cgi::set_geometry(d, &c->p, c->lay, tx, cgi::plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, 0));
+                d.tile_begin = (int)tiles;
+                d.active_steps = (int)std::min<int64_t>(K, r->steps - r->done);
+                if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // launch 0 reads the current buffer
+                tiles += (long long)d.tiles_x * d.tiles_y;
+                table.push_back(d);
+            }
+            if (tiles > INT_MAX / 2) {
+                err = "too many tiles in one chunk";
+                return LBM_E_INVAL;
+            }
+            gtiles[g] = (int)tiles;
         }
         hipError_t e = hipMemcpyAsync(d_slots, table.data(), table.size() * sizeof(cgd::SlotDesc),
                                       hipMemcpyHostToDevice, stream);
-        const int ns = (int)table.size(), nt = (int)tiles;
-        if (e == hipSuccess && (ns != g_nslots || nt != g_tiles || K != g_K)) {
-            if (graph) {
-                (void)hipGraphExecDestroy(graph);
-                graph = nullptr;
+        if ((int)chunks.size() < ng) chunks.resize(ng);
+        for (int g = 0; g < ng && e == hipSuccess; ++g) {
+            Chunk &ch = chunks[g];
+            const int off = first[g], ns = first[g + 1] - first[g], nt = gtiles[g];
+            if (ch.off != off || ch.nslots != ns || ch.tiles != nt || ch.K != K) {
+                if (ch.graph) (void)hipGraphExecDestroy(ch.graph);
+                ch = Chunk{};
+                hipGraph_t gr = nullptr;
+                e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+                hipError_t le = hipSuccess;
+                for (int j = 0; j < K && e == hipSuccess && le == hipSuccess; ++j)
+                    le = cgd::launch_step(storage, tx, d_slots + off, ns, nt, j & 1, j, cap);
+                if (e == hipSuccess) e = hipStreamEndCapture(cap, &gr);
+                if (e == hipSuccess) e = le;
+                if (e == hipSuccess) e = hipGraphInstantiate(&ch.graph, gr, nullptr, nullptr, 0);
+                if (gr) (void)hipGraphDestroy(gr);
+                if (e == hipSuccess) ch = Chunk{ch.graph, off, ns, nt, K};
+                else ch = Chunk{};
             }
-            hipGraph_t gr = nullptr;
-            e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            hipError_t le = hipSuccess;
-            for (int j = 0; j < K && e == hipSuccess && le == hipSuccess; ++j)
-                le = cgd::launch_step(storage, tx, d_slots, ns, nt, j & 1, j, cap);
-            if (e == hipSuccess) e = hipStreamEndCapture(cap, &gr);
-            if (e == hipSuccess) e = le;
-            if (e == hipSuccess) e = hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0);
-            if (gr) (void)hipGraphDestroy(gr);
-            if (e == hipSuccess) {
-                g_nslots = ns;
-                g_tiles = nt;
-                g_K = K;
-            } else {
-                graph = nullptr;
-                g_nslots = g_tiles = g_K = -1;
-            }
+            if (e == hipSuccess) e = hipGraphLaunch(ch.graph, stream);
         }
-        if (e == hipSuccess) e = hipGraphLaunch(graph, stream);
         if (e != hipSuccess) {
             err = hipGetErrorString(e);
             return LBM_E_DEVICE;

@@ -85,3 +85,17 @@ def test_unstable_request_is_isolated():
     assert ra["status"] == capi.LBM_OK
     ref = _alone(good["params"], 500, good["rho_r"], good["rho_b"], None)
     assert np.array_equal(ra["rho_r"], ref["rho_r"]) and np.array_equal(ra["ux"], ref["ux"])
+
+
+def test_served_in_cache_groups_equals_alone():
+    """Active lattices beyond the cache budget run in groups within a chunk."""
+    cases = [W.bubble_cell(g, g, 256, n=1024) for g in (1, 10, 100)]
+    with serve.Server(4 << 30, max_slots=8, chunk_steps=64, storage="f32") as s:
+        ids = [s.enqueue(c["params"], serve.init_disk(512, 512, 256, 1.0, 0.0, 0.0, float(g)), 150, keep_fields=True)
+               for c, g in zip(cases, (1, 10, 100))]
+        res = [s.wait(i, fields=True) for i in ids]
+    for c, r in zip(cases, res):
+        assert r["status"] == capi.LBM_OK and r["steps_done"] == 150
+        ref = _alone(c["params"], 150, c["rho_r"], c["rho_b"], None)
+        for k in ("rho_r", "rho_b", "ux", "uy"):
+            assert np.array_equal(r[k], ref[k]), k
