@@ -122,7 +122,10 @@ int lbm_step(lbm_ctx *ctx, int64_t n);
 int64_t lbm_steps_done(const lbm_ctx *ctx);
 int lbm_sync(lbm_ctx *ctx);
 
-/* Fields at the current step into caller-owned host arrays (any may be NULL);
+/* Fields at the current step into caller-owned host arrays (any may be NULL):
+ * the moments the next collision sees, i.e. of the populations each node
+ * pulls from its neighbours after bounce-back and open-boundary completion
+ * (Sec. 2 eq. (subop4), Sec. 2.5), with the half-force velocity shift;
  * p = sum_k rho_k c_s,k^2 (Sec. 2.1.1 eq. (pressureRelation)).  d (nullable)
  * receives the FP64 diagnostics without the pressure regions.  Synchronises;
  * returns LBM_E_UNSTABLE if a non-finite value was seen. */

@@ -1,0 +1,132 @@
+"""Edge cases of the GPU step against the FP64 oracle: degenerate lattice
+sizes (one node, one row, one column), widths around the 60-column
+wavefront tile and the workgroup span, walls on one- and two-row channels,
+a two-column open channel, one fluid only, no surface tension, recolouring
+strength beta at both ends of its range, and zero steps.  Bound: the FP32
+bound of the static bubble (max |d rho| / rho <= 1e-5, max |d u| <= 1e-6);
+for the rough random fields of the size cases, where that is exceeded, 50
+times the oracle's own sensitivity to FP32 storage rounding."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_01168_amd import capi
+from paper_1903_01168_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 60
+
+
+def say(*a):
+    print("[gpu-edges]", *a, file=sys.stderr, flush=True)
+
+
+def _run(p, rr, rb, ux=None, uy=None, steps=STEPS, color=None, launch=None):
+    s = oracle.Sim(**p).init(rr, rb, ux, uy)
+    if color is not None:
+        s.set_inlet_color(color)
+    s.step(steps)
+    om = s.moments()
+    with capi.Lattice(p) as g:
+        if launch:
+            g.set_launch(*launch)
+        g.init(rr, rb, ux, uy)
+        if color is not None:
+            g.set_inlet_color(color)
+        g.step(steps)
+        gm = g.moments()
+    return om, gm
+
+
+def _errors(om, gm):
+    rho_o = om["rho_r"] + om["rho_b"]
+    drho = float(np.max(np.abs(gm["rho_r"] + gm["rho_b"] - rho_o) / rho_o))
+    du = float(max(np.max(np.abs(gm["ux"] - om["ux"])), np.max(np.abs(gm["uy"] - om["uy"]))))
+    return drho, du
+
+
+def _bounds(p, rr, rb, ux, uy, steps=STEPS):
+    """The fixed FP32 bound, or 50 times the change that rounding its stored
+    populations to FP32 after every step causes in the oracle (rough random
+    fields amplify rounding; the GPU rounds in its arithmetic as well)."""
+    def run(quantise):
+        s = oracle.Sim(**p).init(rr, rb, ux, uy)
+        for _ in range(steps):
+            s.step(1)
+            if quantise:
+                s.set_pops(s.get_pops().astype(np.float32).astype(np.float64))
+        return s.moments()
+    s_rho, s_u = _errors(run(False), run(True))
+    return max(1e-5, 50 * s_rho), max(1e-6, 50 * s_u)
+
+
+SIZES = [(1, 1, "periodic"), (1, 9, "periodic"), (9, 1, "periodic"), (2, 2, "periodic"), (5, 1, "walls"),
+         (5, 2, "walls"), (1, 6, "walls"), (59, 7, "periodic"), (60, 7, "periodic"), (61, 7, "walls"),
+         (119, 5, "periodic"), (121, 5, "walls"), (241, 3, "periodic"), (300, 1, "walls")]
+
+
+@pytest.mark.parametrize("nx,ny,bcy", SIZES)
+def test_degenerate_and_ragged_sizes(nx, ny, bcy):
+    p = W.params(nx=nx, ny=ny, bc_y=bcy, rho0_r=1.0, rho0_b=3.0, tau_r=0.7, tau_b=0.9, A=1e-3,
+                 gx=1e-5 if bcy == "walls" else 0.0)
+    rr, rb, ux, uy = W.random_fields(nx, ny, seed=nx * 31 + ny, rho0_r=1.0, rho0_b=3.0)
+    tol = None
+    for launch in ((64, 0), (256, 1)):
+        drho, du = _errors(*_run(p, rr, rb, ux, uy, launch=launch))
+        if (drho > 1e-5 or du > 1e-6) and tol is None:
+            tol = _bounds(p, rr, rb, ux, uy)
+        t_rho, t_u = tol or (1e-5, 1e-6)
+        say(f"{nx}x{ny} {bcy} tile {launch[0]}: drho/rho {drho:.2e} du {du:.2e} (bounds {t_rho:.1e}, {t_u:.1e})")
+        assert drho <= t_rho and du <= t_u
+
+
+def test_two_column_open_channel():
+    p = W.params(nx=2, ny=6, bc_x="open", bc_y="walls", rho0_r=1.0, rho0_b=2.0, tau_r=0.8, tau_b=0.9, A=1e-3,
+                 u_in_r=0.01, u_in_b=0.01, p_out=0.48)
+    color = np.array([1, 1, 1, -1, -1, -1], dtype=np.int8)
+    rr = np.where(color[:, None] > 0, 1.0, 0.0) * np.ones((1, 2))
+    rb = np.where(color[:, None] > 0, 0.0, 2.0) * np.ones((1, 2))
+    drho, du = _errors(*_run(p, rr, rb, color=color))
+    say(f"open 2x6: drho/rho {drho:.2e} du {du:.2e}")
+    assert drho <= 1e-5 and du <= 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_one_fluid_only(storage):
+    """Blue absent everywhere: it stays exactly zero in every storage, and the
+    red fluid follows the single-phase oracle."""
+    p = W.params(nx=100, ny=20, bc_y="walls", tau_r=0.8, tau_b=0.8, A=1e-3, gx=1e-5, storage=storage)
+    rr = np.ones((20, 100))
+    rb = np.zeros((20, 100))
+    om, gm = _run(p, rr, rb)
+    assert np.all(gm["rho_b"] == 0.0)
+    if storage == "f32":
+        drho, du = _errors(om, gm)
+        assert drho <= 1e-5 and du <= 1e-6
+
+
+@pytest.mark.parametrize("A,beta", [(0.0, 0.7), (1e-3, 0.0), (1e-3, 1.0)])
+def test_surface_tension_and_recolouring_limits(A, beta):
+    c = W.static_bubble(n=48, radius=12)
+    p = dict(c["params"], A=A, beta=beta)
+    drho, du = _errors(*_run(p, c["rho_r"], c["rho_b"], steps=300))
+    say(f"A={A} beta={beta}: drho/rho {drho:.2e} du {du:.2e}")
+    assert drho <= 1e-5 and du <= 1e-6
+
+
+def test_zero_steps():
+    """lbm_step(0) changes nothing; the moments at step 0 (of the pulled
+    initial populations) agree with the oracle's."""
+    c = W.static_bubble(n=40, radius=10)
+    with capi.Lattice(c["params"]) as g:
+        g.init(c["rho_r"], c["rho_b"])
+        before = g.get_pops()
+        g.step(0)
+        assert g.steps_done == 0 and np.array_equal(g.get_pops(), before)
+        gm = g.moments()
+    om = oracle.Sim(**c["params"]).init(c["rho_r"], c["rho_b"], None, None).moments()
+    drho, du = _errors(om, gm)
+    assert drho <= 1e-6 and du <= 1e-7
