@@ -47,9 +47,14 @@ extern "C" {
 #define LBM_E_NOTFOUND (-6) /* unknown request id                                */
 
 /* Face boundary conditions.  x faces: both PERIODIC, or ZOUHE_VELOCITY on
- * x-low with ZOUHE_PRESSURE on x-high.  y faces: both PERIODIC or both
- * BOUNCEBACK (no-slip walls half-way outside the first/last row). */
-enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_ZOUHE_VELOCITY = 2, LBM_BC_ZOUHE_PRESSURE = 3 };
+ * x-low with ZOUHE_PRESSURE on x-high.  y faces: both PERIODIC, or walls
+ * half-way outside the first/last row, each BOUNCEBACK (no slip: a population
+ * that would come from beyond the wall is the node's own opposite one) or
+ * FREESLIP (Sec. 2.5 item 1: diagonal populations are reflected forward along
+ * the wall, i.e. a population that would come from beyond the wall is the
+ * one with the opposite c_y that left the upstream node of the same row). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_ZOUHE_VELOCITY = 2, LBM_BC_ZOUHE_PRESSURE = 3,
+       LBM_BC_FREESLIP = 4 };
 enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 /* Population storage.  Arithmetic is FP32 in every mode.  F32: 72 B per
  * node and buffer.  F16S / BF16S store the eight moving populations of each

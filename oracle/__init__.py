@@ -32,6 +32,7 @@ class OrParams(C.Structure):
         ("gx", C.c_double), ("gy", C.c_double),
         ("u_in_r", C.c_double), ("u_in_b", C.c_double),
         ("p_out", C.c_double),
+        ("slip_lo", C.c_int), ("slip_hi", C.c_int),
     ]
 
 
@@ -168,17 +169,22 @@ class Sim:
 
     Parameters mirror the public ``lbm_params`` struct: ``bc_x`` is
     "periodic" or "open" (velocity inlet west, pressure outlet east),
-    ``bc_y`` is "periodic" or "walls"; ``collision`` is "bgk" or "mrt".
+    ``bc_y`` is "periodic", "walls" (no-slip), "freeslip" (both walls) or
+    "slip_top" (no-slip bottom, free-slip top); ``collision`` is "bgk" or
+    "mrt".
     """
+
+    BC_Y = {"periodic": (0, 0, 0), "walls": (1, 0, 0), "freeslip": (1, 1, 1), "slip_top": (1, 0, 1)}
 
     def __init__(self, nx, ny, *, bc_x="periodic", bc_y="periodic", collision="bgk",
                  percolor=False, rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0,
                  tau_b=1.0, delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8,
                  gx=0.0, gy=0.0, u_in_r=0.0, u_in_b=0.0, p_out=0.0, **_ignored):
         self.nx, self.ny = nx, ny
+        by, slo, shi = self.BC_Y[bc_y]
         p = OrParams(nx=nx, ny=ny,
                      bc_x={"periodic": 0, "open": 1}[bc_x],
-                     bc_y={"periodic": 0, "walls": 1}[bc_y],
+                     bc_y=by, slip_lo=slo, slip_hi=shi,
                      collision={"bgk": 0, "mrt": 1}[collision], percolor=int(percolor),
                      rho0_r=rho0_r, rho0_b=rho0_b, alpha_light=alpha_light,
                      tau_r=tau_r, tau_b=tau_b, delta=delta, A=A, sigma=sigma, beta=beta,

@@ -60,6 +60,14 @@ static int opposite(int i)
     return -1;
 }
 
+/* the direction with the same c_x and the opposite c_y */
+static int mirror_y(int i)
+{
+    for (int j = 0; j < 9; ++j)
+        if (CX[j] == CX[i] && CY[j] == -CY[i]) return j;
+    return i;
+}
+
 /* D2Q9 weights, Sec. 2.1.1 */
 static double Wt(int i)
 {
@@ -369,17 +377,28 @@ static void pass_stream(or_sim *s)
             for (int k = 0; k < 2; ++k)
                 for (int i = 0; i < 9; ++i) {
                     int sx = x - CX[i], sy = y - CY[i];
-                    int outside = 0;
+                    int outside = 0, beyond_wall = 0;
                     if (sy < 0 || sy >= ny) {
                         if (s->p.bc_y == OR_BCY_PERIODIC) sy = wrap(sy, ny);
-                        else outside = 1;
+                        else beyond_wall = sy < 0 ? 1 : 2;
                     }
                     if (sx < 0 || sx >= nx) {
                         if (s->p.bc_x == OR_BCX_PERIODIC) sx = wrap(sx, nx);
                         else outside = 1;
                     }
-                    POP(s->strm, k, i, y, x) = outside ? POP(s->post, k, opposite(i), y, x)
-                                                       : POP(s->post, k, i, sy, sx);
+                    int slip = (beyond_wall == 1 && s->p.slip_lo) || (beyond_wall == 2 && s->p.slip_hi);
+                    double v;
+                    if (beyond_wall && slip && CX[i] != 0 && !outside)
+                        /* free slip: the population that left the upstream node of the
+                           same row towards the wall, reflected in y only */
+                        v = POP(s->post, k, mirror_y(i), y, sx);
+                    else if (beyond_wall || outside)
+                        /* no slip (link bounce-back); at an open face a placeholder that
+                           the Zou-He completion overwrites */
+                        v = POP(s->post, k, opposite(i), y, x);
+                    else
+                        v = POP(s->post, k, i, sy, sx);
+                    POP(s->strm, k, i, y, x) = v;
                 }
 }
 

@@ -25,7 +25,7 @@ extern "C" {
 #endif
 
 enum { OR_BCX_PERIODIC = 0, OR_BCX_OPEN = 1 };   /* open: velocity inlet at x=0, pressure outlet at x=nx-1 */
-enum { OR_BCY_PERIODIC = 0, OR_BCY_WALLS = 1 };  /* walls: no-slip, halfway (link) bounce-back */
+enum { OR_BCY_PERIODIC = 0, OR_BCY_WALLS = 1 };  /* walls: halfway (link) reflection, see slip_lo/hi */
 enum { OR_BGK = 0, OR_MRT = 1 };
 
 typedef struct {
@@ -44,6 +44,8 @@ typedef struct {
     double gx, gy;          /* body force per unit mass */
     double u_in_r, u_in_b;  /* inlet x-velocity of a red / blue inlet node */
     double p_out;           /* outlet pressure */
+    int slip_lo, slip_hi;   /* walls: 0 no-slip (bounce-back), 1 free-slip (specular reflection,
+                               Sec. 2.5 item 1) at y = -1/2 and y = ny - 1/2 */
 } or_params;
 
 typedef struct or_sim or_sim;

@@ -16,7 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcglbm.so")
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_BUSY, LBM_E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6
-BC = {"periodic": 0, "bounceback": 1, "zouhe_velocity": 2, "zouhe_pressure": 3}
+BC = {"periodic": 0, "bounceback": 1, "zouhe_velocity": 2, "zouhe_pressure": 3, "freeslip": 4}
+# y-face pairs (low, high) by the ``bc_y`` names of ``workloads.params``
+BC_Y = {"periodic": ("periodic", "periodic"), "walls": ("bounceback", "bounceback"),
+        "freeslip": ("freeslip", "freeslip"), "slip_top": ("bounceback", "freeslip")}
 COLL = {"bgk": 0, "mrt": 1}
 STORE = {"f32": 0, "f16s": 1, "bf16s": 2}
 
@@ -111,13 +114,12 @@ def load(path: str = LIB_PATH):
 def make_params(p: dict) -> LbmParams:
     """C struct from a parameter dict (keys of ``workloads.params``)."""
     xper = p.get("bc_x", "periodic") == "periodic"
-    yper = p.get("bc_y", "periodic") == "periodic"
+    ylo, yhi = BC_Y[p.get("bc_y", "periodic")]
     return LbmParams(
         nx=int(p["nx"]), ny=int(p["ny"]),
         bc_xlo=BC["periodic"] if xper else BC["zouhe_velocity"],
         bc_xhi=BC["periodic"] if xper else BC["zouhe_pressure"],
-        bc_ylo=BC["periodic"] if yper else BC["bounceback"],
-        bc_yhi=BC["periodic"] if yper else BC["bounceback"],
+        bc_ylo=BC[ylo], bc_yhi=BC[yhi],
         collision=COLL[p.get("collision", "bgk")], storage=STORE[p.get("storage", "f32")],
         rho0_r=p["rho0_r"], rho0_b=p["rho0_b"], alpha_light=p["alpha_light"],
         tau_r=p["tau_r"], tau_b=p["tau_b"], delta=p["delta"], A=p["A"], sigma=p["sigma"],

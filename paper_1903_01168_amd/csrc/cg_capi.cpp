@@ -74,8 +74,11 @@ int validate(const lbm_params *p, std::string &msg)
     }
     if (!xper && p->nx < 2) { msg = "an open x direction needs nx >= 2"; return LBM_E_INVAL; }
     const bool yper = p->bc_ylo == LBM_BC_PERIODIC && p->bc_yhi == LBM_BC_PERIODIC;
-    const bool ywall = p->bc_ylo == LBM_BC_BOUNCEBACK && p->bc_yhi == LBM_BC_BOUNCEBACK;
-    if (!yper && !ywall) { msg = "y faces: both periodic or both bounce-back"; return LBM_E_INVAL; }
+    auto wall = [](int b) { return b == LBM_BC_BOUNCEBACK || b == LBM_BC_FREESLIP; };
+    const bool ywall = wall(p->bc_ylo) && wall(p->bc_yhi);
+    if (!yper && !ywall) {
+        msg = "y faces: both periodic, or each a bounce-back or free-slip wall"; return LBM_E_INVAL;
+    }
     if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_MRT) { msg = "unknown collision"; return LBM_E_INVAL; }
     if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16S) { msg = "unknown storage"; return LBM_E_INVAL; }
     if (!(p->rho0_r > 0 && p->rho0_b > 0)) { msg = "rho0 must be > 0"; return LBM_E_INVAL; }
@@ -163,6 +166,8 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
     if (p->bc_xlo == LBM_BC_PERIODIC) f |= cgd::F_XPER;
     else f |= cgd::F_XOPEN;
     if (p->bc_ylo == LBM_BC_PERIODIC) f |= cgd::F_YPER;
+    if (p->bc_ylo == LBM_BC_FREESLIP) f |= cgd::F_SLIP_LO;
+    if (p->bc_yhi == LBM_BC_FREESLIP) f |= cgd::F_SLIP_HI;
     if (p->collision == LBM_COLL_MRT) f |= cgd::F_MRT;
     if (p->sigma > 0) f |= cgd::F_SIGMA;
     if (p->gx != 0.0 || p->gy != 0.0) f |= cgd::F_FORCE;

@@ -27,10 +27,19 @@ __host__ __device__ constexpr int vclass(int i) { return i == 0 ? 0 : (i <= 4 ? 
 __host__ __device__ constexpr float wgt(int i) { return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f); }
 __host__ __device__ constexpr float bco(int i) { return i == 0 ? -4.0f / 27.0f : (i <= 4 ? 2.0f / 27.0f : 5.0f / 108.0f); }
 
+// the direction with the same c_x and the opposite c_y (free-slip reflection)
+__host__ __device__ constexpr int mirror_y(int i)
+{
+    return i == 2 ? 4 : i == 4 ? 2 : i == 5 ? 8 : i == 8 ? 5 : i == 6 ? 7 : i == 7 ? 6 : i;
+}
+
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "axis opposites");
+static_assert(cx(mirror_y(5)) == cx(5) && cy(mirror_y(5)) == -cy(5) && cx(mirror_y(6)) == cx(6) &&
+              cy(mirror_y(6)) == -cy(6), "mirror directions");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
 
-enum : int { F_XPER = 1, F_XOPEN = 2, F_YPER = 4, F_MRT = 8, F_SIGMA = 16, F_FORCE = 32 };
+enum : int { F_XPER = 1, F_XOPEN = 2, F_YPER = 4, F_MRT = 8, F_SIGMA = 16, F_FORCE = 32, F_SLIP_LO = 64,
+             F_SLIP_HI = 128 };
 enum : int { ST_F32 = 0, ST_F16S = 1, ST_BF16S = 2 };
 
 // ------------------------------------------------------------- descriptor --
@@ -358,10 +367,12 @@ __device__ __forceinline__ XCols make_cols(const SlotDesc &S, int x)
 
 // One real row: scalar byte offsets of the source rows for c_y = -1, 0, +1
 // and whether that neighbour row lies beyond a wall (then: bounce-back from
-// the node's own opposite population).
+// the node's own opposite population, or for a free-slip wall the mirrored
+// population of the upstream node of the same row).
 struct RowSrc {
     uint32_t off[3];
     bool wall[3];
+    bool slip[3];
     int y;
 };
 
@@ -377,6 +388,7 @@ __device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y)
         const bool out = sy < 0 || sy >= S.ny;
         if (out && per) sy = wrapi(sy, S.ny);
         r.wall[d + 1] = out && !per;
+        r.slip[d + 1] = out && !per && (S.flags & (sy < 0 ? F_SLIP_LO : F_SLIP_HI));
         r.off[d + 1] = (uint32_t)((out && !per) ? y : sy) * (uint32_t)S.pitch * Codec<ST>::bytes;
     }
     return r;
@@ -404,9 +416,13 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
                 continue;
             }
             const int dy = cy(i) + 1;
-            // bounce-back: the node's own opposite population (same row and column)
-            const uint32_t soff = rw.wall[dy] ? plane_off<ST>(opp(i), pb) + rw.off[1] : plane_off<ST>(i, pb) + rw.off[dy];
-            const uint32_t voff = rw.wall[dy] ? xc.o0 : xc.col(cx(i));
+            // beyond a wall: no slip takes the node's own opposite population
+            // (same row and column); free slip the mirrored diagonal of the
+            // upstream node of the same row (a wall-normal one bounces back)
+            const bool fs = cx(i) != 0 && rw.slip[dy];
+            const uint32_t soff = rw.wall[dy] ? plane_off<ST>(fs ? mirror_y(i) : opp(i), pb) + rw.off[1]
+                                              : plane_off<ST>(i, pb) + rw.off[dy];
+            const uint32_t voff = rw.wall[dy] && !fs ? xc.o0 : xc.col(cx(i));
             raw.v[k * 9 + i] = C::load(h.r[k], voff, soff);
         }
     return raw;

@@ -17,7 +17,8 @@ available; the paper's sizes and parameters are quoted where they exist):
 * ``gravity_slug``   -- periodic channel with walls, body force, alternating
   heavy/light slugs (Sec. 5.1 periodic case).
 * ``inlet_outlet``   -- channel with a velocity inlet, pressure outlet and
-  walls; the inlet colour alternates on a seeded schedule (Sec. 5.2).
+  free-slip walls, stratified two-phase inflow (Sec. 5.2 open channel).
+* ``serve_trace``    -- a seeded mix of bubble and slug solve requests.
 """
 from __future__ import annotations
 
@@ -179,9 +180,10 @@ def inlet_schedule(total_steps, seed=0, lo=300, hi=800, first_red=True):
 
 def inlet_outlet(seed=0, nx=8192, ny=512, gamma=5, u_in=0.01, A=1e-3, beta=0.7, tau_heavy=0.6,
                  gas_fraction=0.2, storage="f32", collision="bgk", alternating=False, M=None,
-                 total_steps=200000):
+                 walls="freeslip", total_steps=200000):
     """Channel with a west velocity inlet, an east pressure outlet and walls
-    top/bottom, set up as the paper's open-channel case (Sec. 5.2): heavy
+    top/bottom (``walls``: "freeslip" as in the paper, or "walls" for no
+    slip), set up as the paper's open-channel case (Sec. 5.2): heavy
     liquid (red, rho0_r = gamma) below light gas (blue), volume fractions
     0.8 / 0.2 in the initial fill and in the inflow, which enters with u_in in
     both phases; mu_g = mu_l / 2 (or nu_heavy / nu_light = M / gamma when M is
@@ -193,7 +195,7 @@ def inlet_outlet(seed=0, nx=8192, ny=512, gamma=5, u_in=0.01, A=1e-3, beta=0.7, 
     nu_h = nu_from_tau(tau_heavy)
     nu_l = nu_h * gamma / 2.0 if M is None else nu_h * gamma / M
     p0 = 0.48   # rho0_light * 3 (1 - 0.2) / 5
-    p = params(nx=nx, ny=ny, bc_x="open", bc_y="walls", rho0_r=float(gamma), rho0_b=1.0,
+    p = params(nx=nx, ny=ny, bc_x="open", bc_y=walls, rho0_r=float(gamma), rho0_b=1.0,
                tau_r=tau_heavy, tau_b=tau_from_nu(nu_l), A=A, beta=beta, u_in_r=u_in,
                u_in_b=u_in, p_out=p0, storage=storage, collision=collision)
     visc = "mu_g=mu_l/2" if M is None else f"M={M}"

@@ -71,8 +71,9 @@ def test_validation_rejects(lib, bad):
 
 
 def test_validation_accepts(lib):
-    for kw in (dict(), dict(bc_x="open", p_out=0.48), dict(bc_y="walls", gx=1e-6),
-               dict(collision="mrt"), dict(storage="bf16s"), dict(A=0.0, sigma=1e-3)):
+    for kw in (dict(), dict(bc_x="open", p_out=0.48), dict(bc_y="walls", gx=1e-6), dict(bc_y="freeslip"),
+               dict(bc_y="slip_top", bc_x="open", p_out=0.48), dict(collision="mrt"), dict(storage="bf16s"),
+               dict(A=0.0, sigma=1e-3)):
         base = dict(nx=16, ny=8, A=1e-3)
         base.update(kw)
         assert _bytes(W.params(**base)) > 0
@@ -87,4 +88,10 @@ def test_unpaired_faces_rejected(lib):
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
     cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3))
     cp.bc_ylo = cp.bc_yhi = capi.BC["zouhe_velocity"]
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3))
+    cp.bc_ylo = capi.BC["freeslip"]                     # a wall against a periodic face
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3))
+    cp.bc_xlo = cp.bc_xhi = capi.BC["freeslip"]         # free slip is a y-face condition
     assert lib.lbm_bytes_required(C.byref(cp)) == 0

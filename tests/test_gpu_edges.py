@@ -65,13 +65,14 @@ def _bounds(p, rr, rb, ux, uy, steps=STEPS):
 
 SIZES = [(1, 1, "periodic"), (1, 9, "periodic"), (9, 1, "periodic"), (2, 2, "periodic"), (5, 1, "walls"),
          (5, 2, "walls"), (1, 6, "walls"), (59, 7, "periodic"), (60, 7, "periodic"), (61, 7, "walls"),
-         (119, 5, "periodic"), (121, 5, "walls"), (241, 3, "periodic"), (300, 1, "walls")]
+         (119, 5, "periodic"), (121, 5, "walls"), (241, 3, "periodic"), (300, 1, "walls"),
+         (1, 4, "freeslip"), (7, 1, "freeslip"), (61, 2, "slip_top"), (125, 6, "freeslip")]
 
 
 @pytest.mark.parametrize("nx,ny,bcy", SIZES)
 def test_degenerate_and_ragged_sizes(nx, ny, bcy):
     p = W.params(nx=nx, ny=ny, bc_y=bcy, rho0_r=1.0, rho0_b=3.0, tau_r=0.7, tau_b=0.9, A=1e-3,
-                 gx=1e-5 if bcy == "walls" else 0.0)
+                 gx=1e-5 if bcy != "periodic" else 0.0)
     rr, rb, ux, uy = W.random_fields(nx, ny, seed=nx * 31 + ny, rho0_r=1.0, rho0_b=3.0)
     tol = None
     for launch in ((64, 0), (256, 1)):

@@ -116,6 +116,11 @@ CASES = {
                       tau_b=0.6, A=1e-3, gx=1e-5),
     "sigma_mode": dict(nx=256, ny=48, rho0_r=1.0, rho0_b=2.0, tau_r=0.6, tau_b=1.5, sigma=4e-4),
     "narrow_periodic": dict(nx=70, ny=5, rho0_r=1.0, rho0_b=1.0, tau_r=1.0, tau_b=0.75, A=2e-3, beta=0.99),
+    # free-slip walls (Sec. 2.5 item 1), both sides, and no-slip bottom with free-slip top
+    "freeslip_force": dict(nx=150, ny=21, bc_y="freeslip", rho0_r=1.0, rho0_b=3.0, tau_r=0.8, tau_b=0.6,
+                           A=1e-3, gx=1e-5, gy=-2e-6),
+    "slip_top_mrt": dict(nx=110, ny=17, bc_y="slip_top", collision="mrt", rho0_r=1.0, rho0_b=4.0, tau_r=0.9,
+                         tau_b=0.7, A=1e-3, gx=1e-5),
 }
 
 
@@ -326,13 +331,14 @@ def test_batch_bit_identical_to_single(storage):
         lat.close()
 
 
-def _open_case():
+def _open_case(bc_y="walls"):
     p, rr, rb, color = _stratified_channel(96, 20, 5.0)
-    return dict(params=p, rho_r=rr, rho_b=rb, color=color)
+    return dict(params=dict(p, bc_y=bc_y), rho_r=rr, rho_b=rb, color=color)
 
 
 ONE_STEP = {
     "open_g5": _open_case,
+    "open_g5_freeslip": lambda: _open_case("freeslip"),
     "bubble_g10": lambda: W.bubble_cell(10, 10, 20, n=64),
     "bubble_g10_mrt": lambda: W.bubble_cell(10, 1, 20, n=64, collision="mrt"),
     "slug_g10": lambda: W.gravity_slug(nx=256, ny=32, gamma=10, Re=100, g=1e-5, band_lo=40, band_hi=90),

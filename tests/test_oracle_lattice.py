@@ -283,3 +283,67 @@ def test_open_channel_inlet_colour(orc):
     assert np.all(m["rho_b"][:, 0] == 0) and np.all(m["rho_r"][:, 0] > 0)
     assert m["rho_r"][:, :10].sum() > 0.5 * m["rho_r"].sum()
     assert np.allclose(m["p"][:, -1], 0.48, rtol=1e-12)
+
+
+# ------------------------------------------------------------ free-slip walls
+def _single_phase(orc, nx, ny, bc_y, tau, g, steps, collision="bgk"):
+    p = dict(nx=nx, ny=ny, bc_y=bc_y, tau_r=tau, tau_b=tau, A=0.0, gx=g, collision=collision)
+    s = orc.Sim(**p).init(np.ones((ny, nx)), np.zeros((ny, nx)))
+    s.step(steps)
+    return s.moments()
+
+
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_freeslip_channel_is_plug_flow(orc, collision):
+    """Free-slip walls on both sides (Sec. 2.5 item 1) take no momentum from
+    the flow: under a body force the fluid accelerates as a plug, u_x = (n +
+    1/2) g at every node after n steps (half-force velocity), u_y = 0."""
+    g, n = 1e-5, 40
+    m = _single_phase(orc, 7, 10, "freeslip", 0.8, g, n, collision)
+    assert np.allclose(m["ux"], (n + 0.5) * g, rtol=1e-12, atol=0)
+    assert np.max(np.abs(m["uy"])) < 1e-14          # round-off of the y-momentum sum
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.3])
+def test_freeslip_top_is_a_mirror_plane(orc, tau):
+    """Specular reflection at the top wall equals a symmetry plane: a channel
+    with a no-slip bottom and a free-slip top evolves exactly as the lower half
+    of a no-slip channel twice as wide, step by step."""
+    ny, g, n = 9, 1e-6, 300
+    half = _single_phase(orc, 5, ny, "slip_top", tau, g, n)
+    full = _single_phase(orc, 5, 2 * ny, "walls", tau, g, n)
+    # velocities of 1e-5 from populations of 0.1: round-off leaves ~1e-11 relative
+    assert np.allclose(half["ux"], full["ux"][:ny], rtol=1e-9, atol=0)
+    assert np.allclose(full["ux"][:ny], full["ux"][ny:][::-1], rtol=1e-9, atol=0)
+
+
+def test_freeslip_conserves_each_colour(orc):
+    c = W.gravity_slug(seed=2, nx=128, ny=16, gamma=10, Re=10, g=1e-5, band_lo=20, band_hi=50)
+    p = dict(c["params"], bc_y="freeslip")
+    s = orc.Sim(**p).init(c["rho_r"], c["rho_b"])
+    m0 = _totals(s.moments())
+    s.step(500)
+    m1 = _totals(s.moments())
+    assert abs(m1[0] / m0[0] - 1) < 1e-13 and abs(m1[1] / m0[1] - 1) < 1e-13
+
+
+def test_freeslip_mirror_plane_with_rough_fields(orc):
+    """The mirror equivalence with fields that vary along x (a population
+    taken from the wrong column would break it): random density and velocity
+    in a 24 x 7 channel with a free-slip top against the 24 x 14 no-slip
+    channel holding the same fields and their mirror image above."""
+    nx, ny, n = 24, 7, 60
+    rng = np.random.default_rng(5)
+    rho = 1.0 + 0.02 * rng.standard_normal((ny, nx))
+    ux = 0.01 * rng.standard_normal((ny, nx))
+    uy = 0.01 * rng.standard_normal((ny, nx))
+    p = dict(nx=nx, tau_r=0.9, tau_b=0.9, A=0.0, gx=1e-5)
+    half = orc.Sim(ny=ny, bc_y="slip_top", **p).init(rho, 0 * rho, ux, uy)
+    full = orc.Sim(ny=2 * ny, bc_y="walls", **p).init(np.vstack([rho, rho[::-1]]), np.zeros((2 * ny, nx)),
+                                                       np.vstack([ux, ux[::-1]]), np.vstack([uy, -uy[::-1]]))
+    half.step(n)
+    full.step(n)
+    mh, mf = half.moments(), full.moments()
+    assert np.allclose(mh["rho_r"], mf["rho_r"][:ny], rtol=1e-12, atol=0)
+    assert np.allclose(mh["ux"], mf["ux"][:ny], rtol=0, atol=1e-13)
+    assert np.allclose(mh["uy"], mf["uy"][:ny], rtol=0, atol=1e-13)
