@@ -33,6 +33,7 @@ class OrParams(C.Structure):
         ("u_in_r", C.c_double), ("u_in_b", C.c_double),
         ("p_out", C.c_double),
         ("slip_lo", C.c_int), ("slip_hi", C.c_int),
+        ("contact_angle", C.c_double),
     ]
 
 
@@ -67,6 +68,7 @@ def lib():
         L.or_omega_eff.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
         L.or_gradient3x3.argtypes = [_D, _D]
         L.or_perturbation.argtypes = [_D, C.c_double, _D]
+        L.or_wetting.argtypes = [_D, _D, C.c_double, _D]
         L.or_recolor.argtypes = [_D, C.c_double, C.c_double, _D, C.c_double, C.c_double,
                                  C.c_double, _D, _D]
         L.or_zouhe_west.restype = C.c_double
@@ -159,6 +161,14 @@ def mrt_collide(N, Neq, omega, lam=0.8):
     return out
 
 
+def wetting(F2, ns2, theta):
+    """Sec. 2.4: the colour gradient turned to the angle theta (radians) with
+    the wall normal ns (into the fluid)."""
+    out = np.zeros(2)
+    lib().or_wetting(_p(_f64(F2)), _p(_f64(ns2)), float(theta), _p(out))
+    return out
+
+
 def threads():
     return lib().or_threads()
 
@@ -179,7 +189,7 @@ class Sim:
     def __init__(self, nx, ny, *, bc_x="periodic", bc_y="periodic", collision="bgk",
                  percolor=False, rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0,
                  tau_b=1.0, delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8,
-                 gx=0.0, gy=0.0, u_in_r=0.0, u_in_b=0.0, p_out=0.0, **_ignored):
+                 gx=0.0, gy=0.0, u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0, **_ignored):
         self.nx, self.ny = nx, ny
         by, slo, shi = self.BC_Y[bc_y]
         p = OrParams(nx=nx, ny=ny,
@@ -189,7 +199,7 @@ class Sim:
                      rho0_r=rho0_r, rho0_b=rho0_b, alpha_light=alpha_light,
                      tau_r=tau_r, tau_b=tau_b, delta=delta, A=A, sigma=sigma, beta=beta,
                      mrt_lambda=mrt_lambda, gx=gx, gy=gy, u_in_r=u_in_r, u_in_b=u_in_b,
-                     p_out=p_out)
+                     p_out=p_out, contact_angle=contact_angle)
         self._params = p
         self._h = lib().or_create(C.byref(p))
         if not self._h:

@@ -53,6 +53,8 @@ static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 static int cls(int i) { return CX[i] * CX[i] + CY[i] * CY[i]; }
 
+static const double PI_ = 3.14159265358979323846;
+
 static int opposite(int i)
 {
     for (int j = 0; j < 9; ++j)
@@ -164,6 +166,29 @@ void or_gradient3x3(const double *psi9, double *F2)
         F2[0] += xi(i) * CX[i] * v;
         F2[1] += xi(i) * CY[i] * v;
     }
+}
+
+/* Sec. 2.4: orientation of the colour gradient at a fluid node next to a
+ * wall.  n* = F/|F|; the two unit normals that make the angle theta with
+ * the wall normal ns; the one closer to n* (ns itself on a tie); |F| kept. */
+void or_wetting(const double *F2, const double *ns2, double theta, double *out2)
+{
+    double Fm = sqrt(F2[0] * F2[0] + F2[1] * F2[1]);
+    out2[0] = F2[0];
+    out2[1] = F2[1];
+    if (Fm <= 1e-12) return;                 /* no gradient, nothing to orient (R5) */
+    double nx = F2[0] / Fm, ny = F2[1] / Fm;
+    double c = cos(theta), s = sin(theta);
+    double n1x = ns2[0] * c - ns2[1] * s, n1y = ns2[1] * c + ns2[0] * s;
+    double n2x = ns2[0] * c + ns2[1] * s, n2y = ns2[1] * c - ns2[0] * s;
+    double D1 = sqrt((nx - n1x) * (nx - n1x) + (ny - n1y) * (ny - n1y));
+    double D2 = sqrt((nx - n2x) * (nx - n2x) + (ny - n2y) * (ny - n2y));
+    double ox, oy;
+    if (D1 < D2) { ox = n1x; oy = n1y; }
+    else if (D1 > D2) { ox = n2x; oy = n2y; }
+    else { ox = ns2[0]; oy = ns2[1]; }
+    out2[0] = Fm * ox;
+    out2[1] = Fm * oy;
 }
 
 /* Sec. 2.2 eq. (perturbation), colour-blind sum (R5): the term added to N* */
@@ -546,6 +571,15 @@ static void pass_collide(or_sim *s)
                 for (int dx = -1; dx <= 1; ++dx)
                     patch[(dy + 1) * 3 + (dx + 1)] = s->psi[(size_t)(y + 1 + dy) * (nx + 2) + (x + 1 + dx)];
             or_gradient3x3(patch, F);
+            if (p->bc_y == OR_BCY_WALLS && p->contact_angle >= 0.0 && (y == 0 || y == ny - 1)) {
+                /* wetting (Sec. 2.4, R11): the wall normal points into the fluid and
+                   the gradient points into red, so the angle between them is the
+                   contact angle measured through blue, pi minus red's */
+                double ns[2] = {0.0, y == 0 ? 1.0 : -1.0}, Fw[2];
+                or_wetting(F, ns, PI_ * (1.0 - p->contact_angle / 180.0), Fw);
+                F[0] = Fw[0];
+                F[1] = Fw[1];
+            }
             double psi = patch[4];
             double w = or_omega_eff(psi, s->omega[0], s->omega[1], p->delta);
             double A = p->sigma > 0.0 ? 9.0 * p->sigma * w / 4.0 : p->A;

@@ -46,6 +46,8 @@ typedef struct {
     double p_out;           /* outlet pressure */
     int slip_lo, slip_hi;   /* walls: 0 no-slip (bounce-back), 1 free-slip (specular reflection,
                                Sec. 2.5 item 1) at y = -1/2 and y = ny - 1/2 */
+    double contact_angle;   /* walls: static contact angle of the red fluid, measured through red,
+                               in degrees (Sec. 2.4); < 0: no adjustment of the colour gradient */
 } or_params;
 
 typedef struct or_sim or_sim;
@@ -58,6 +60,11 @@ void   or_equilibrium(double rho_k, double ux, double uy, double alpha_k, double
 double or_omega_eff(double psi, double omega_r, double omega_b, double delta);
 void   or_gradient3x3(const double *psi9, double *F2);   /* psi9[(dy+1)*3+(dx+1)] */
 void   or_perturbation(const double *F2, double A, double *out9); /* the added term */
+/* Sec. 2.4: the colour gradient F2 of a fluid node next to a wall with unit
+ * normal ns (pointing into the fluid) turned to make the angle theta (radians,
+ * measured between the gradient and ns) with the wall: the closer of the two
+ * candidates, its length kept. */
+void   or_wetting(const double *F2, const double *ns2, double theta, double *out2);
 void   or_recolor(const double *Nss9, double rho_r, double rho_b, const double *F2, double beta,
                   double alpha_r, double alpha_b, double *out_r9, double *out_b9);
 double or_zouhe_west(double *N9, double vx, double vy);   /* completes 1,5,8; returns rho */

@@ -220,3 +220,36 @@ def test_mrt_reduces_to_bgk_and_relaxes_moments(orc):
         dm = M @ (out - N)
         s = np.array([lam * w] * 7 + [w, w])
         assert np.allclose(dm, -s * (M @ (N - E)), atol=1e-14)
+
+
+# ------------------------------------------------------------- wetting (Sec. 2.4)
+def test_wetting_keeps_length_and_sets_the_angle(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        F = rng.standard_normal(2)
+        a = rng.uniform(0, 2 * np.pi)
+        ns = np.array([np.cos(a), np.sin(a)])
+        theta = rng.uniform(0.05, np.pi - 0.05)
+        out = orc.wetting(F, ns, theta)
+        Fm = np.linalg.norm(F)
+        assert np.linalg.norm(out) == pytest.approx(Fm, rel=1e-13)
+        assert out @ ns == pytest.approx(Fm * np.cos(theta), abs=1e-12 * Fm)
+        # the chosen direction is the candidate closer to F's own direction
+        t = np.array([-ns[1], ns[0]])
+        other = Fm * (np.cos(theta) * ns - np.sign(out @ t) * np.sin(theta) * t)
+        assert np.linalg.norm(out / Fm - F / Fm) <= np.linalg.norm(other / Fm - F / Fm) + 1e-12
+
+
+def test_wetting_special_cases(orc):
+    ns = np.array([0.0, 1.0])
+    F = np.array([0.3, -0.4])
+    # already at the angle: unchanged
+    th = np.arccos((F @ ns) / np.linalg.norm(F))
+    assert np.allclose(orc.wetting(F, ns, th), F, atol=1e-14)
+    # along the normal: a tie, the normal itself
+    assert np.allclose(orc.wetting(np.array([0.0, 2.0]), ns, 1.0), [0.0, 2.0], atol=1e-15)
+    # no gradient: nothing changes
+    assert np.all(orc.wetting(np.zeros(2), ns, 1.0) == 0.0)
+    # mirror symmetry: F mirrored across the normal gives the mirrored result
+    a, b = orc.wetting(F, ns, 1.1), orc.wetting(F * [-1, 1], ns, 1.1)
+    assert np.allclose(a * [-1, 1], b, atol=1e-15)
