@@ -57,11 +57,13 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_ZOUHE_VELOCITY = 2, LB
        LBM_BC_FREESLIP = 4 };
 enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 /* Population storage.  Arithmetic is FP32 in every mode.  F32: 72 B per
- * node and buffer.  F16S / BF16S store the eight moving populations of each
- * colour as 16-bit deviations (N/rho0_k - phi~_k,i) * 2^s from the rest state
- * of the colour (phi~ = phi rounded to the 16-bit format; stochastic
- * rounding), and the rest population in FP32, holding the node's exact
- * colour-mass remainder: 40 B per node and buffer. */
+ * node and buffer (9 red + 9 blue planes).  F16S / BF16S: for each moving
+ * direction the colour-blind population N_i as a 16-bit (FP16 or BF16)
+ * deviation (N_i - rho0_k phi^k_i) 2^12 / max(rho0_r, rho0_b) from the rest
+ * state (the reference is the same for both fluids) and the red share
+ * N^r_i / N_i as a 16-bit fixed-point fraction; the two rest populations in
+ * FP32, each absorbing its node's exact colour-mass remainder; stochastic
+ * rounding throughout.  40 B per node and buffer. */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16S = 1, LBM_STORE_BF16S = 2 };
 
 typedef struct {
@@ -80,6 +82,18 @@ typedef struct {
     double gx, gy;           /* body force per unit mass (Guo forcing)                   */
     double u_in_r, u_in_b;   /* inlet x-velocity of red / blue inlet nodes               */
     double p_out;            /* outlet pressure                                          */
+    /* Static contact angle at y walls (Sec. 2.4): with wetting = 1, the colour
+     * gradient of every node of the first and last row is turned, its length
+     * kept, to the closer of the two directions that make the angle
+     * 180 - contact_angle with the wall normal pointing into the fluid (the
+     * gradient points into red, so contact_angle is the red fluid's angle,
+     * measured through red; a tangential part of exactly 0 keeps the normal;
+     * 0 and 180 turn every gradient onto the normal).  Needs y walls (either
+     * kind).  wetting = 0 (zero-initialised struct): no adjustment, and
+     * contact_angle is ignored. */
+    int32_t wetting;         /* 0 or 1                                                   */
+    int32_t reserved0;       /* must be 0                                                */
+    double contact_angle;    /* degrees, 0 <= contact_angle <= 180                       */
 } lbm_params;
 
 typedef struct {

@@ -170,7 +170,9 @@ void or_gradient3x3(const double *psi9, double *F2)
 
 /* Sec. 2.4: orientation of the colour gradient at a fluid node next to a
  * wall.  n* = F/|F|; the two unit normals that make the angle theta with
- * the wall normal ns; the one closer to n* (ns itself on a tie); |F| kept. */
+ * the wall normal ns; the one closer to n* (ns itself on a tie); |F| kept.
+ * At theta = 0 or pi the two candidates are one vector, which is taken: the
+ * tie rule is read as meant for n* halfway between two distinct ones (R11). */
 void or_wetting(const double *F2, const double *ns2, double theta, double *out2)
 {
     double Fm = sqrt(F2[0] * F2[0] + F2[1] * F2[1]);
@@ -179,6 +181,11 @@ void or_wetting(const double *F2, const double *ns2, double theta, double *out2)
     if (Fm <= 1e-12) return;                 /* no gradient, nothing to orient (R5) */
     double nx = F2[0] / Fm, ny = F2[1] / Fm;
     double c = cos(theta), s = sin(theta);
+    if (fabs(s) <= 1e-15) {                  /* theta = 0 or pi: the two candidates coincide (R11) */
+        out2[0] = Fm * c * ns2[0];
+        out2[1] = Fm * c * ns2[1];
+        return;
+    }
     double n1x = ns2[0] * c - ns2[1] * s, n1y = ns2[1] * c + ns2[0] * s;
     double n2x = ns2[0] * c + ns2[1] * s, n2y = ns2[1] * c - ns2[0] * s;
     double D1 = sqrt((nx - n1x) * (nx - n1x) + (ny - n1y) * (ny - n1y));

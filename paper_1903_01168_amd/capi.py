@@ -40,6 +40,7 @@ class LbmParams(C.Structure):
         ("A", C.c_double), ("sigma", C.c_double), ("beta", C.c_double), ("mrt_lambda", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double),
         ("u_in_r", C.c_double), ("u_in_b", C.c_double), ("p_out", C.c_double),
+        ("wetting", C.c_int32), ("reserved0", C.c_int32), ("contact_angle", C.c_double),
     ]
 
 
@@ -115,6 +116,7 @@ def make_params(p: dict) -> LbmParams:
     """C struct from a parameter dict (keys of ``workloads.params``)."""
     xper = p.get("bc_x", "periodic") == "periodic"
     ylo, yhi = BC_Y[p.get("bc_y", "periodic")]
+    ca = float(p.get("contact_angle", -1.0))        # < 0: no wetting adjustment
     return LbmParams(
         nx=int(p["nx"]), ny=int(p["ny"]),
         bc_xlo=BC["periodic"] if xper else BC["zouhe_velocity"],
@@ -124,7 +126,8 @@ def make_params(p: dict) -> LbmParams:
         rho0_r=p["rho0_r"], rho0_b=p["rho0_b"], alpha_light=p["alpha_light"],
         tau_r=p["tau_r"], tau_b=p["tau_b"], delta=p["delta"], A=p["A"], sigma=p["sigma"],
         beta=p["beta"], mrt_lambda=p["mrt_lambda"], gx=p["gx"], gy=p["gy"],
-        u_in_r=p["u_in_r"], u_in_b=p["u_in_b"], p_out=p["p_out"])
+        u_in_r=p["u_in_r"], u_in_b=p["u_in_b"], p_out=p["p_out"],
+        wetting=1 if ca >= 0 else 0, contact_angle=ca if ca >= 0 else 0.0)
 
 
 def _f64(a, shape):

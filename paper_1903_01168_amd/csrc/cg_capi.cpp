@@ -96,6 +96,13 @@ int validate(const lbm_params *p, std::string &msg)
     if (!xper && !(p->p_out > 0)) { msg = "p_out must be > 0 with an open outlet"; return LBM_E_INVAL; }
     if (!xper && !(std::fabs(p->u_in_r) < 1 && std::fabs(p->u_in_b) < 1)) { msg = "|u_in| must be < 1"; return LBM_E_INVAL; }
     if (!std::isfinite(p->gx) || !std::isfinite(p->gy)) { msg = "non-finite body force"; return LBM_E_INVAL; }
+    if ((p->wetting != 0 && p->wetting != 1) || p->reserved0 != 0) {
+        msg = "wetting must be 0 or 1 and reserved0 0"; return LBM_E_INVAL;
+    }
+    if (p->wetting && yper) { msg = "a contact angle needs y walls"; return LBM_E_INVAL; }
+    if (p->wetting && !(p->contact_angle >= 0 && p->contact_angle <= 180)) {
+        msg = "contact_angle must be in [0, 180] degrees"; return LBM_E_INVAL;
+    }
     return LBM_OK;
 }
 
@@ -171,7 +178,15 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
     if (p->collision == LBM_COLL_MRT) f |= cgd::F_MRT;
     if (p->sigma > 0) f |= cgd::F_SIGMA;
     if (p->gx != 0.0 || p->gy != 0.0) f |= cgd::F_FORCE;
+    if (p->wetting) f |= cgd::F_WET;
     d.flags = f;
+    // wetting (Sec. 2.4): the gradient makes the angle 180 - contact_angle
+    // with the wall normal; its cosine and sine, exact at 0 and 180 degrees
+    const double ca = p->wetting ? p->contact_angle : 90.0;
+    const double rad = ca * (3.14159265358979323846 / 180.0);
+    const bool end = ca == 0.0 || ca == 180.0;
+    d.wet_c = end ? (ca == 0.0 ? -1.f : 1.f) : (float)-std::cos(rad);
+    d.wet_s = end ? 0.f : (float)std::sin(rad);
 }
 
 // One wavefront per workgroup suits lattices up to a few million nodes (finer

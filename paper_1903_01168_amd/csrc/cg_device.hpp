@@ -39,7 +39,7 @@ static_assert(cx(mirror_y(5)) == cx(5) && cy(mirror_y(5)) == -cy(5) && cx(mirror
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
 
 enum : int { F_XPER = 1, F_XOPEN = 2, F_YPER = 4, F_MRT = 8, F_SIGMA = 16, F_FORCE = 32, F_SLIP_LO = 64,
-             F_SLIP_HI = 128 };
+             F_SLIP_HI = 128, F_WET = 256 };
 enum : int { ST_F32 = 0, ST_F16S = 1, ST_BF16S = 2 };
 
 // ------------------------------------------------------------- descriptor --
@@ -70,6 +70,9 @@ struct SlotDesc {
     float mref[3];                // rho0_k phi^k_c by class c ([0] unused)
     float dscale, dmul;           // deviation scale 2^12 / max(rho0) and its inverse
     float rest0[2];               // rho0_k phi^k_0: reference of the FP32 rest population
+    // wetting (F_WET): cosine and sine of the angle between the adjusted
+    // colour gradient and the wall normal (180 degrees - contact angle)
+    float wet_c, wet_s;
 };
 
 // ------------------------------------------------------------------ codec --
@@ -707,6 +710,26 @@ __device__ __forceinline__ void mrt_inv(const float *m, float *f)
     f[6] = dg - px + py - a8;
     f[7] = dg - px - py + a8;
     f[8] = dg + px - py - a8;
+}
+
+// Wetting (Sec. 2.4) at a node of the first (bottom) or last row next to a
+// wall, whose normal into the fluid is (0, 1) or (0, -1).  Of the two unit
+// vectors at the angle a = 180 degrees - contact angle from the normal, the
+// one closer to F/|F| is the one whose tangential part has the sign of F_x
+// (their distances to F/|F| differ by 4 sin(a) F_x / |F| in the square, so
+// the sign decides without the distances' cancellation); F_x = 0 is the tie,
+// which keeps the normal; at a = 0 or 180 degrees both are the one vector
+// (0, +-cos a) of the normal's line.  |F| is kept; no gradient, no change.
+__device__ __forceinline__ void wet(const SlotDesc &S, bool bottom, float &Fx, float &Fy)
+{
+    const float F2 = Fx * Fx + Fy * Fy;
+    if (!(F2 > 1e-24f)) return;
+    const float Fm = __builtin_sqrtf(F2);
+    const float s = S.wet_s;
+    const float tx = Fx > 0.f ? s : (Fx < 0.f ? -s : 0.f);
+    const float ty = (Fx == 0.f && s != 0.f) ? 1.f : S.wet_c;   // along the normal (0, 1) of the bottom
+    Fx = Fm * tx;
+    Fy = Fm * (bottom ? ty : -ty);
 }
 
 // Collision (Sec. 2.1.1 BGK / Sec. 2.1.2 MRT, colour-blind), perturbation

@@ -157,8 +157,9 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
         if (out_lane) {
             // S2I4 gradient, Sec. 2.2 eq. (colorGradient): xi = 1/3 axis, 1/12 diagonal;
             // rows y+1 / y-1 are ahead / behind when marching up, the reverse when down
-            const float Fx = (1.f / 3.f) * (p0.e - p0.w) + (1.f / 12.f) * ((pa.e - pa.w) + (pb.e - pb.w));
-            const float Fy = fd * ((1.f / 3.f) * (pa.c - pb.c) + (1.f / 12.f) * ((pa.e + pa.w) - (pb.e + pb.w)));
+            float Fx = (1.f / 3.f) * (p0.e - p0.w) + (1.f / 12.f) * ((pa.e - pa.w) + (pb.e - pb.w));
+            float Fy = fd * ((1.f / 3.f) * (pa.c - pb.c) + (1.f / 12.f) * ((pa.e + pa.w) - (pb.e + pb.w)));
+            if ((S.flags & F_WET) && (y == 0 || y == ny - 1)) wet(S, y == 0, Fx, Fy);
             float outr[9], outb[9];
             collide(S, cur, p0.c, Fx, Fy, outr, outb);
             if (ST == ST_F32) conserve(cur, outr, outb);   // 16-bit storage rounds far coarser

@@ -18,6 +18,8 @@ available; the paper's sizes and parameters are quoted where they exist):
   heavy/light slugs (Sec. 5.1 periodic case).
 * ``inlet_outlet``   -- channel with a velocity inlet, pressure outlet and
   free-slip walls, stratified two-phase inflow (Sec. 5.2 open channel).
+* ``wall_droplet``   -- a rectangular droplet on a wall relaxing to a
+  prescribed contact angle (Sec. 2.4; the paper's contact-angle case).
 * ``serve_trace``    -- a seeded mix of bubble and slug solve requests.
 """
 from __future__ import annotations
@@ -29,7 +31,7 @@ import numpy as np
 DEFAULTS = dict(bc_x="periodic", bc_y="periodic", collision="bgk", storage="f32",
                 rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0, tau_b=1.0,
                 delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8, gx=0.0, gy=0.0,
-                u_in_r=0.0, u_in_b=0.0, p_out=0.0)
+                u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0)
 
 
 def params(**kw):
@@ -209,6 +211,25 @@ def inlet_outlet(seed=0, nx=8192, ny=512, gamma=5, u_in=0.01, A=1e-3, beta=0.7, 
     return dict(name=f"inlet-outlet {nx}x{ny} gamma={gamma} {visc} stratified", params=p,
                 rho_r=rr, rho_b=rb, ux=None, uy=None,
                 inlet_color=np.where(heavy, 1, -1).astype(np.int8))
+
+
+def wall_droplet(contact_angle, n=100, sigma=0.01, tau=1.0, beta=0.7, bc_y="walls", storage="f32",
+                 collision="bgk"):
+    """Contact-angle case (Sec. 6 of the paper's comparison, its contact-angle
+    figure): an n x n lattice, density and viscosity ratio 1, surface
+    tension sigma = 0.01, walls at the bottom and top, periodic in x; a red
+    rectangle of 2 round(0.165 n) x round(0.165 n) nodes sits on the bottom
+    wall, centred on the lattice's middle (for even n its axis falls between
+    two columns and the case is mirror-symmetric), in blue.  The red fluid's contact angle (degrees) is prescribed
+    at both walls."""
+    w, h = 2 * int(round(0.165 * n)), int(round(0.165 * n))     # even width: a centred axis
+    y, x = np.mgrid[0:n, 0:n]
+    x0 = (n - w) // 2
+    red = ((x >= x0) & (x < x0 + w) & (y < h)).astype(np.float64)
+    p = params(nx=n, ny=n, bc_y=bc_y, rho0_r=1.0, rho0_b=1.0, tau_r=tau, tau_b=tau, sigma=sigma, beta=beta,
+               contact_angle=float(contact_angle), storage=storage, collision=collision)
+    return dict(name=f"droplet_{contact_angle:g}", params=p, rho_r=red, rho_b=1.0 - red, ux=None, uy=None,
+                contact_angle=float(contact_angle))
 
 
 def random_fields(nx, ny, seed=0, rho0_r=1.0, rho0_b=1.0, umax=0.02, smooth=True):

@@ -63,6 +63,7 @@ def test_layout_sizes(lib):
     dict(A=1e-3, sigma=1e-3), dict(alpha_light=1.0), dict(delta=0.0),
     dict(bc_x="open", p_out=0.0), dict(bc_x="open", nx=1, p_out=0.48),
     dict(bc_x="open", p_out=0.48, u_in_r=1.5),
+    dict(contact_angle=60.0), dict(bc_y="walls", contact_angle=181.0),
 ])
 def test_validation_rejects(lib, bad):
     kw = dict(nx=16, ny=8, A=1e-3)
@@ -73,7 +74,8 @@ def test_validation_rejects(lib, bad):
 def test_validation_accepts(lib):
     for kw in (dict(), dict(bc_x="open", p_out=0.48), dict(bc_y="walls", gx=1e-6), dict(bc_y="freeslip"),
                dict(bc_y="slip_top", bc_x="open", p_out=0.48), dict(collision="mrt"), dict(storage="bf16s"),
-               dict(A=0.0, sigma=1e-3)):
+               dict(A=0.0, sigma=1e-3), dict(bc_y="walls", contact_angle=60.0),
+               dict(bc_y="slip_top", contact_angle=0.0), dict(bc_y="freeslip", contact_angle=180.0)):
         base = dict(nx=16, ny=8, A=1e-3)
         base.update(kw)
         assert _bytes(W.params(**base)) > 0
@@ -94,4 +96,19 @@ def test_unpaired_faces_rejected(lib):
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
     cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3))
     cp.bc_xlo = cp.bc_xhi = capi.BC["freeslip"]         # free slip is a y-face condition
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+
+
+def test_wetting_fields_validated(lib):
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3, bc_y="walls"))
+    assert cp.wetting == 0 and lib.lbm_bytes_required(C.byref(cp)) > 0
+    cp.contact_angle = float("nan")                     # ignored while wetting is 0
+    assert lib.lbm_bytes_required(C.byref(cp)) > 0
+    cp.wetting = 1
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp.contact_angle = 45.0
+    assert lib.lbm_bytes_required(C.byref(cp)) > 0
+    cp.wetting = 2
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp.wetting, cp.reserved0 = 1, 7
     assert lib.lbm_bytes_required(C.byref(cp)) == 0

@@ -343,6 +343,7 @@ ONE_STEP = {
     "bubble_g10_mrt": lambda: W.bubble_cell(10, 1, 20, n=64, collision="mrt"),
     "slug_g10": lambda: W.gravity_slug(nx=256, ny=32, gamma=10, Re=100, g=1e-5, band_lo=40, band_hi=90),
     "bubble_g1": lambda: W.static_bubble(n=64, radius=16),
+    "droplet_wet120": lambda: W.wall_droplet(120.0, n=64),
 }
 
 

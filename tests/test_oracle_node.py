@@ -253,3 +253,13 @@ def test_wetting_special_cases(orc):
     # mirror symmetry: F mirrored across the normal gives the mirrored result
     a, b = orc.wetting(F, ns, 1.1), orc.wetting(F * [-1, 1], ns, 1.1)
     assert np.allclose(a * [-1, 1], b, atol=1e-15)
+
+
+def test_wetting_end_angles(orc):
+    """theta = 0 and pi: the two candidates coincide, every gradient is turned
+    onto +ns or -ns with its length kept (whatever its tangential part)."""
+    ns = np.array([0.0, -1.0])
+    for F in ([0.3, -0.4], [-0.3, 0.4], [0.0, 0.5], [0.5, 0.0]):
+        F = np.array(F)
+        assert np.allclose(orc.wetting(F, ns, 0.0), np.linalg.norm(F) * ns, atol=1e-15)
+        assert np.allclose(orc.wetting(F, ns, np.pi), -np.linalg.norm(F) * ns, atol=1e-15)
