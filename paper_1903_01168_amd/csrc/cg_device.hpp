@@ -369,13 +369,11 @@ __device__ __forceinline__ XCols make_cols(const SlotDesc &S, int x)
 }
 
 // One real row: scalar byte offsets of the source rows for c_y = -1, 0, +1
-// and whether that neighbour row lies beyond a wall (then: bounce-back from
-// the node's own opposite population, or for a free-slip wall the mirrored
-// population of the upstream node of the same row).
+// (the row itself where that neighbour lies beyond a wall).  Which
+// neighbours lie beyond a wall follows from y alone and is derived where it
+// is needed, so that nothing else stays live in scalar registers.
 struct RowSrc {
     uint32_t off[3];
-    bool wall[3];
-    bool slip[3];
     int y;
 };
 
@@ -390,8 +388,6 @@ __device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y)
         int sy = y - d;
         const bool out = sy < 0 || sy >= S.ny;
         if (out && per) sy = wrapi(sy, S.ny);
-        r.wall[d + 1] = out && !per;
-        r.slip[d + 1] = out && !per && (S.flags & (sy < 0 ? F_SLIP_LO : F_SLIP_HI));
         r.off[d + 1] = (uint32_t)((out && !per) ? y : sy) * (uint32_t)S.pitch * Codec<ST>::bytes;
     }
     return r;
@@ -410,6 +406,23 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
     using C = Codec<ST>;
     Raw18<ST> raw;
     const uint32_t pb = (uint32_t)S.plane * C::bytes;
+    // walls: populations with c_y = +1 come from beyond the bottom wall in row
+    // 0, those with c_y = -1 from beyond the top wall in row ny - 1
+    const bool ywall = !(S.flags & F_YPER);
+    const bool wlo = ywall && rw.y == 0, whi = ywall && rw.y == S.ny - 1;
+    if (!(wlo || whi)) {                   // every row away from a wall (uniform branch)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if (rest32<ST>() && i == 0) {   // own node, FP32 plane: offsets twice the 16-bit ones
+                    raw.r0[k] = load_f32raw(h.r[k], 2u * xc.o0, 2u * rw.off[1]);
+                    continue;
+                }
+                raw.v[k * 9 + i] = C::load(h.r[k], xc.col(cx(i)), plane_off<ST>(i, pb) + rw.off[cy(i) + 1]);
+            }
+        return raw;
+    }
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
@@ -419,13 +432,15 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
                 continue;
             }
             const int dy = cy(i) + 1;
+            const bool wall = cy(i) > 0 ? wlo : (cy(i) < 0 ? whi : false);
+            const bool slip = wall && (S.flags & (cy(i) > 0 ? F_SLIP_LO : F_SLIP_HI));
             // beyond a wall: no slip takes the node's own opposite population
             // (same row and column); free slip the mirrored diagonal of the
             // upstream node of the same row (a wall-normal one bounces back)
-            const bool fs = cx(i) != 0 && rw.slip[dy];
-            const uint32_t soff = rw.wall[dy] ? plane_off<ST>(fs ? mirror_y(i) : opp(i), pb) + rw.off[1]
-                                              : plane_off<ST>(i, pb) + rw.off[dy];
-            const uint32_t voff = rw.wall[dy] && !fs ? xc.o0 : xc.col(cx(i));
+            const bool fs = cx(i) != 0 && slip;
+            const uint32_t soff = wall ? plane_off<ST>(fs ? mirror_y(i) : opp(i), pb) + rw.off[1]
+                                       : plane_off<ST>(i, pb) + rw.off[dy];
+            const uint32_t voff = wall && !fs ? xc.o0 : xc.col(cx(i));
             raw.v[k * 9 + i] = C::load(h.r[k], voff, soff);
         }
     return raw;
