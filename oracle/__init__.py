@@ -34,6 +34,7 @@ class OrParams(C.Structure):
         ("p_out", C.c_double),
         ("slip_lo", C.c_int), ("slip_hi", C.c_int),
         ("contact_angle", C.c_double),
+        ("ns_correction", C.c_int),
     ]
 
 
@@ -72,9 +73,11 @@ def lib():
         L.or_recolor.argtypes = [_D, C.c_double, C.c_double, _D, C.c_double, C.c_double,
                                  C.c_double, _D, _D]
         L.or_zouhe_west.restype = C.c_double
-        L.or_zouhe_west.argtypes = [_D, C.c_double, C.c_double]
+        L.or_zouhe_west.argtypes = [_D, C.c_double, C.c_double, C.c_double]
         L.or_zouhe_east.restype = C.c_double
-        L.or_zouhe_east.argtypes = [_D, C.c_double, C.c_double]
+        L.or_zouhe_east.argtypes = [_D, C.c_double, C.c_double, C.c_double]
+        L.or_equilibrium_hermite.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _D]
+        L.or_ns_source.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _D]
         L.or_mrt_matrices.argtypes = [_D, _D]
         L.or_mrt_collide.argtypes = [_D, _D, C.c_double, C.c_double, _D]
         _LIB = L
@@ -114,6 +117,20 @@ def equilibrium(rho_k, ux, uy, alpha_k):
     return out
 
 
+def equilibrium_hermite(rho_k, ux, uy, alpha_k):
+    """Sec. 2.1.3 eq. (equilibrium_hermite)."""
+    out = np.zeros(9)
+    lib().or_equilibrium_hermite(rho_k, ux, uy, alpha_k, _p(out))
+    return out
+
+
+def ns_source(dqx, dqy, s1, s7):
+    """Sec. 2.1.3: U = M^-1 C of the Navier-Stokes correction."""
+    out = np.zeros(9)
+    lib().or_ns_source(dqx, dqy, s1, s7, _p(out))
+    return out
+
+
 def omega_eff(psi, omega_r, omega_b, delta=0.1):
     return lib().or_omega_eff(psi, omega_r, omega_b, delta)
 
@@ -137,15 +154,15 @@ def recolor(Nss, rho_r, rho_b, F, beta, alpha_r, alpha_b):
     return r, b
 
 
-def zouhe_west(N, vx, vy):
+def zouhe_west(N, vx, vy, kap=0.0):
     N = _f64(N).copy()
-    rho = lib().or_zouhe_west(_p(N), vx, vy)
+    rho = lib().or_zouhe_west(_p(N), vx, vy, kap)
     return rho, N
 
 
-def zouhe_east(N, rho, vy):
+def zouhe_east(N, rho, vy, kap=0.0):
     N = _f64(N).copy()
-    vx = lib().or_zouhe_east(_p(N), rho, vy)
+    vx = lib().or_zouhe_east(_p(N), rho, vy, kap)
     return vx, N
 
 
@@ -189,7 +206,8 @@ class Sim:
     def __init__(self, nx, ny, *, bc_x="periodic", bc_y="periodic", collision="bgk",
                  percolor=False, rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0,
                  tau_b=1.0, delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8,
-                 gx=0.0, gy=0.0, u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0, **_ignored):
+                 gx=0.0, gy=0.0, u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0,
+                 ns_correction=False, **_ignored):
         self.nx, self.ny = nx, ny
         by, slo, shi = self.BC_Y[bc_y]
         p = OrParams(nx=nx, ny=ny,
@@ -199,7 +217,7 @@ class Sim:
                      rho0_r=rho0_r, rho0_b=rho0_b, alpha_light=alpha_light,
                      tau_r=tau_r, tau_b=tau_b, delta=delta, A=A, sigma=sigma, beta=beta,
                      mrt_lambda=mrt_lambda, gx=gx, gy=gy, u_in_r=u_in_r, u_in_b=u_in_b,
-                     p_out=p_out, contact_angle=contact_angle)
+                     p_out=p_out, contact_angle=contact_angle, ns_correction=int(bool(ns_correction)))
         self._params = p
         self._h = lib().or_create(C.byref(p))
         if not self._h:

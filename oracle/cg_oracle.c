@@ -35,6 +35,21 @@
  *      from the domain; outlet densities rho_k = chi_k p_out / c_s,k^2.
  *  R8  collision is colour-blind (same omega_eff and S for both colours); the
  *      percolor switch runs the per-colour form for comparison.
+ *  R6b free slip (Sec. 2.5 item 1): a diagonal population that would come
+ *      from beyond the wall is the mirrored one that left the upstream node of
+ *      the same row; the wall-normal one bounces back.
+ *  R11 contact angle (Sec. 2.4): theta is the red fluid's angle, measured
+ *      through red; the gradient (into red) is turned to pi - theta from the
+ *      wall normal; at theta = 0 or pi the two candidates are one vector.
+ *  R12 Hermite equilibrium (Sec. 2.1.3): the garbled factor (3 c_i - 4) read
+ *      as (3 |c_i|^2 - 4).
+ *  R13 Navier-Stokes source (Sec. 2.1.3): C_7 = (1 - s_7/2)(dQx/dx - dQy/dy)
+ *      (printed with a factor 3, omega_eff and a plus sign).
+ *  R14 Q^k = (1.8 alpha_k - 0.8) rho_k u with the half-force velocity; its
+ *      ghost values beyond walls and open faces follow the colour field's
+ *      rules (R6): parity unpinned (the paper gives no rule; pinned are the
+ *      periodic decay rates).  Zou-He H uses the prescribed (inlet) or
+ *      measured (outlet) colour fractions of R7.
  */
 #include "cg_oracle.h"
 
@@ -132,6 +147,30 @@ void or_alphas(double rho0_r, double rho0_b, double alpha_light, double *alpha_r
     }
 }
 
+/* Appendix B, as printed */
+static const double MRT_M[81] = {
+     1,  1,  1,  1,  1,  1,  1,  1,  1,
+    -4, -1, -1, -1, -1,  2,  2,  2,  2,
+     4, -2, -2, -2, -2,  1,  1,  1,  1,
+     0,  1,  0, -1,  0,  1, -1, -1,  1,
+     0, -2,  0,  2,  0,  1, -1, -1,  1,
+     0,  0,  1,  0, -1,  1,  1, -1, -1,
+     0,  0, -2,  0,  2,  1,  1, -1, -1,
+     0,  1, -1,  1, -1,  0,  0,  0,  0,
+     0,  0,  0,  0,  0,  1, -1,  1, -1,
+};
+static const double MRT_MINV36[81] = {
+    4, -4,  4,  0,  0,  0,  0,  0,  0,
+    4, -1, -2,  6, -6,  0,  0,  9,  0,
+    4, -1, -2,  0,  0,  6, -6, -9,  0,
+    4, -1, -2, -6,  6,  0,  0,  9,  0,
+    4, -1, -2,  0,  0, -6,  6, -9,  0,
+    4,  2,  1,  6,  3,  6,  3,  0,  9,
+    4,  2,  1, -6, -3,  6,  3,  0, -9,
+    4,  2,  1, -6, -3, -6, -3,  0,  9,
+    4,  2,  1,  6,  3, -6, -3,  0, -9,
+};
+
 /* Sec. 2.1.1 eq. (equilibrium) */
 void or_equilibrium(double rho_k, double ux, double uy, double alpha_k, double *out9)
 {
@@ -139,6 +178,38 @@ void or_equilibrium(double rho_k, double ux, double uy, double alpha_k, double *
     for (int i = 0; i < 9; ++i) {
         double cu = CX[i] * ux + CY[i] * uy;
         out9[i] = rho_k * (phi(i, alpha_k) + Wt(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+/* Sec. 2.1.3 eq. (equilibrium_hermite): the linear term carries the factor
+ * 1 + (3 c_s^2 - 1)(3 |c_i|^2 - 4) / 2 (R12: |c_i|^2 for the garbled c_i;
+ * with it the equilibrium keeps mass and momentum and its third moments
+ * sum c_x^2 c_y, sum c_x c_y^2 become c_s^2 rho u_y, c_s^2 rho u_x). */
+void or_equilibrium_hermite(double rho_k, double ux, double uy, double alpha_k, double *out9)
+{
+    double uu = ux * ux + uy * uy;
+    double k3 = 3.0 * (3.0 * (1.0 - alpha_k) / 5.0) - 1.0;     /* 3 c_s^2 - 1 */
+    for (int i = 0; i < 9; ++i) {
+        double cu = CX[i] * ux + CY[i] * uy;
+        double lin = 3.0 * cu * (1.0 + 0.5 * k3 * (3.0 * cls(i) - 4.0));
+        out9[i] = rho_k * (phi(i, alpha_k) + Wt(i) * (lin + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+/* Sec. 2.1.3: the source U = M^{-1} C added to the MRT collision, with
+ * C = (0, C_1, 0, 0, 0, 0, 0, C_7, 0), C_1 = 3 (1 - s_1/2) (dQx/dx + dQy/dy)
+ * and (R13) C_7 = (1 - s_7/2) (dQx/dx - dQy/dy): row 1 of M is
+ * 3 (c_x^2 + c_y^2) - 4 and row 7 is c_x^2 - c_y^2, and the lattice's
+ * remaining third-moment defect sum c_x^3 N^e - 3 c_s^2 rho u_x = Q_x (and
+ * likewise in y) enters the momentum flux as diag(dQx/dx, dQy/dy). */
+void or_ns_source(double dQxdx, double dQydy, double s1, double s7, double *out9)
+{
+    double Cm[9] = {0.0};
+    Cm[1] = 3.0 * (1.0 - s1 / 2.0) * (dQxdx + dQydy);
+    Cm[7] = (1.0 - s7 / 2.0) * (dQxdx - dQydy);
+    for (int i = 0; i < 9; ++i) {
+        out9[i] = 0.0;
+        for (int j = 0; j < 9; ++j) out9[i] += MRT_MINV36[i * 9 + j] / 36.0 * Cm[j];
     }
 }
 
@@ -233,49 +304,30 @@ void or_recolor(const double *Nss9, double rho_r, double rho_b, const double *F2
 }
 
 /* Sec. 2.5 item 3, velocity inlet rotated to the west face (R7).
- * Unknowns 1, 5, 8; the non-equilibrium bounce-back closes the system. */
-double or_zouhe_west(double *N, double vx, double vy)
+ * Unknowns 1, 5, 8; the non-equilibrium bounce-back closes the system.
+ * kap = sum_k chi_k (3 c_s,k^2 - 1) with the Hermite equilibrium of
+ * Sec. 2.1.3 (its corrective term H = kap rho v_x / 3), 0 with the plain one. */
+double or_zouhe_west(double *N, double vx, double vy, double kap)
 {
     double rho = (N[0] + N[2] + N[4] + 2.0 * (N[3] + N[6] + N[7])) / (1.0 - vx);
-    N[1] = N[3] + 2.0 / 3.0 * rho * vx;
-    N[5] = N[7] - 0.5 * (N[2] - N[4]) + 0.5 * rho * vy + rho * vx / 6.0;
-    N[8] = N[6] + 0.5 * (N[2] - N[4]) - 0.5 * rho * vy + rho * vx / 6.0;
+    double H = kap * rho * vx / 3.0;
+    N[1] = N[3] + 2.0 / 3.0 * rho * vx - H;
+    N[5] = N[7] - 0.5 * (N[2] - N[4]) + 0.5 * rho * vy + rho * vx / 6.0 + 0.5 * H;
+    N[8] = N[6] + 0.5 * (N[2] - N[4]) - 0.5 * rho * vy + rho * vx / 6.0 + 0.5 * H;
     return rho;
 }
 
-/* Sec. 2.5 item 3, pressure outlet rotated to the east face (R7). */
-double or_zouhe_east(double *N, double rho, double vy)
+/* Sec. 2.5 item 3, pressure outlet rotated to the east face (R7); kap as
+ * for the inlet. */
+double or_zouhe_east(double *N, double rho, double vy, double kap)
 {
     double vx = (N[0] + N[2] + N[4] + 2.0 * (N[1] + N[5] + N[8])) / rho - 1.0;
-    N[3] = N[1] - 2.0 / 3.0 * rho * vx;
-    N[6] = N[8] - 0.5 * (N[2] - N[4]) + 0.5 * rho * vy - rho * vx / 6.0;
-    N[7] = N[5] + 0.5 * (N[2] - N[4]) - 0.5 * rho * vy - rho * vx / 6.0;
+    double H = kap * rho * vx / 3.0;
+    N[3] = N[1] - 2.0 / 3.0 * rho * vx + H;
+    N[6] = N[8] - 0.5 * (N[2] - N[4]) + 0.5 * rho * vy - rho * vx / 6.0 - 0.5 * H;
+    N[7] = N[5] + 0.5 * (N[2] - N[4]) - 0.5 * rho * vy - rho * vx / 6.0 - 0.5 * H;
     return vx;
 }
-
-/* Appendix B, as printed */
-static const double MRT_M[81] = {
-     1,  1,  1,  1,  1,  1,  1,  1,  1,
-    -4, -1, -1, -1, -1,  2,  2,  2,  2,
-     4, -2, -2, -2, -2,  1,  1,  1,  1,
-     0,  1,  0, -1,  0,  1, -1, -1,  1,
-     0, -2,  0,  2,  0,  1, -1, -1,  1,
-     0,  0,  1,  0, -1,  1,  1, -1, -1,
-     0,  0, -2,  0,  2,  1,  1, -1, -1,
-     0,  1, -1,  1, -1,  0,  0,  0,  0,
-     0,  0,  0,  0,  0,  1, -1,  1, -1,
-};
-static const double MRT_MINV36[81] = {
-    4, -4,  4,  0,  0,  0,  0,  0,  0,
-    4, -1, -2,  6, -6,  0,  0,  9,  0,
-    4, -1, -2,  0,  0,  6, -6, -9,  0,
-    4, -1, -2, -6,  6,  0,  0,  9,  0,
-    4, -1, -2,  0,  0, -6,  6, -9,  0,
-    4,  2,  1,  6,  3,  6,  3,  0,  9,
-    4,  2,  1, -6, -3,  6,  3,  0, -9,
-    4,  2,  1, -6, -3, -6, -3,  0,  9,
-    4,  2,  1,  6,  3, -6, -3,  0, -9,
-};
 
 void or_mrt_matrices(double *M81, double *Minv81)
 {
@@ -329,6 +381,7 @@ struct or_sim {
     double *rho;    /* [2][ny][nx] colour densities used by the step    */
     double *ux, *uy;
     double *psi;    /* [ny+2][nx+2] colour field with ghost layer        */
+    double *q;      /* [2 colours][2 components][ny+2][nx+2] Q^k of Sec. 2.1.3 with ghost layer */
     signed char *inlet_color;
     long step;
 };
@@ -355,6 +408,7 @@ or_sim *or_create(const or_params *p)
     s->ux = (double *)calloc(n, sizeof(double));
     s->uy = (double *)calloc(n, sizeof(double));
     s->psi = (double *)calloc((size_t)(p->nx + 2) * (p->ny + 2), sizeof(double));
+    s->q = (double *)calloc(4 * (size_t)(p->nx + 2) * (p->ny + 2), sizeof(double));
     s->inlet_color = (signed char *)malloc((size_t)p->ny);
     memset(s->inlet_color, 1, (size_t)p->ny);
     return s;
@@ -369,8 +423,17 @@ void or_destroy(or_sim *s)
     free(s->ux);
     free(s->uy);
     free(s->psi);
+    free(s->q);
     free(s->inlet_color);
     free(s);
+}
+
+/* the equilibrium in use: Sec. 2.1.3's Hermite form with the Navier-Stokes
+ * correction, else Sec. 2.1.1's */
+static void equilibrium(const or_sim *s, double rho_k, double ux, double uy, int k, double *out9)
+{
+    if (s->p.ns_correction) or_equilibrium_hermite(rho_k, ux, uy, s->alpha[k], out9);
+    else or_equilibrium(rho_k, ux, uy, s->alpha[k], out9);
 }
 
 /* initial state: equilibrium of the given fields (Sec. 2.1.1 eq. (equilibrium)) */
@@ -382,9 +445,9 @@ int or_init(or_sim *s, const double *rho_r, const double *rho_b, const double *u
             size_t c = (size_t)y * nx + x;
             double u = ux ? ux[c] : 0.0, v = uy ? uy[c] : 0.0;
             double e[9];
-            or_equilibrium(rho_r[c], u, v, s->alpha[0], e);
+            equilibrium(s, rho_r[c], u, v, 0, e);
             for (int i = 0; i < 9; ++i) POP(s->post, 0, i, y, x) = e[i];
-            or_equilibrium(rho_b[c], u, v, s->alpha[1], e);
+            equilibrium(s, rho_b[c], u, v, 1, e);
             for (int i = 0; i < 9; ++i) POP(s->post, 1, i, y, x) = e[i];
         }
     s->step = 0;
@@ -458,7 +521,9 @@ static void pass_densities_and_open_bc(or_sim *s)
             int red = s->inlet_color[y] > 0;
             double chi[2] = {red ? 1.0 : 0.0, red ? 0.0 : 1.0};
             double vx = red ? s->p.u_in_r : s->p.u_in_b;
-            double rho_in = or_zouhe_west(N, vx, 0.0);
+            double kap = s->p.ns_correction ? chi[0] * (3.0 * s->cs2[0] - 1.0) + chi[1] * (3.0 * s->cs2[1] - 1.0)
+                                            : 0.0;
+            double rho_in = or_zouhe_west(N, vx, 0.0, kap);
             static const int unk[3] = {1, 5, 8};
             for (int k = 0; k < 2; ++k) {
                 for (int j = 0; j < 3; ++j) POP(s->strm, k, unk[j], y, x) = chi[k] * N[unk[j]];
@@ -476,7 +541,9 @@ static void pass_densities_and_open_bc(or_sim *s)
             double chi[2] = {vol_r / (vol_r + vol_b), vol_b / (vol_r + vol_b)};
             double rk[2] = {chi[0] * s->p.p_out / s->cs2[0], chi[1] * s->p.p_out / s->cs2[1]};
             for (int i = 0; i < 9; ++i) N[i] = POP(s->strm, 0, i, y, x) + POP(s->strm, 1, i, y, x);
-            or_zouhe_east(N, rk[0] + rk[1], 0.0);
+            double kap = s->p.ns_correction ? chi[0] * (3.0 * s->cs2[0] - 1.0) + chi[1] * (3.0 * s->cs2[1] - 1.0)
+                                            : 0.0;
+            or_zouhe_east(N, rk[0] + rk[1], 0.0, kap);
             static const int unk[3] = {3, 6, 7};
             for (int k = 0; k < 2; ++k) {
                 for (int j = 0; j < 3; ++j) POP(s->strm, k, unk[j], y, x) = chi[k] * N[unk[j]];
@@ -513,14 +580,15 @@ static double color_field(const or_sim *s, double rho_r, double rho_b)
     return (a - b) / (a + b);
 }
 
-/* psi at (x, y) in [-1, nx] x [-1, ny], ghost rules of R6 */
-static double psi_ghost(const or_sim *s, int x, int y)
+/* value of a field f ([ny+2][nx+2] with ghost layer) at (x, y) in
+ * [-1, nx] x [-1, ny], ghost rules of R6 */
+static double ghost_value(const or_sim *s, const double *f, int x, int y)
 {
     int nx = s->p.nx, ny = s->p.ny;
     if (s->p.bc_x == OR_BCX_PERIODIC) x = wrap(x, nx);
     if (s->p.bc_y == OR_BCY_PERIODIC) y = wrap(y, ny);
     int xin = x >= 0 && x < nx, yin = y >= 0 && y < ny;
-    if (xin && yin) return s->psi[(size_t)(y + 1) * (nx + 2) + (x + 1)];
+    if (xin && yin) return f[(size_t)(y + 1) * (nx + 2) + (x + 1)];
     if (!yin) {
         /* wall (solid) node: W-weighted mean over fluid neighbours, Sec. 2.4 */
         double num = 0.0, den = 0.0;
@@ -528,35 +596,76 @@ static double psi_ghost(const or_sim *s, int x, int y)
             int fx = x + CX[i], fy = y + CY[i];
             if (s->p.bc_x == OR_BCX_PERIODIC) fx = wrap(fx, nx);
             if (fx < 0 || fx >= nx || fy < 0 || fy >= ny) continue;
-            num += Wt(i) * s->psi[(size_t)(fy + 1) * (nx + 2) + (fx + 1)];
+            num += Wt(i) * f[(size_t)(fy + 1) * (nx + 2) + (fx + 1)];
             den += Wt(i);
         }
         return num / den;
     }
     /* open-boundary ghost column: nearest in-domain column */
     int cxn = x < 0 ? 0 : nx - 1;
-    return s->psi[(size_t)(y + 1) * (nx + 2) + (cxn + 1)];
+    return f[(size_t)(y + 1) * (nx + 2) + (cxn + 1)];
 }
 
-/* Pass 4: colour field on the domain, then the ghost layer */
+/* fill the ghost layer of f: ghost columns first (they only read the
+ * domain), then ghost rows */
+static void fill_ghosts(const or_sim *s, double *f)
+{
+    int nx = s->p.nx, ny = s->p.ny;
+    for (int y = 0; y < ny; ++y) {
+        f[(size_t)(y + 1) * (nx + 2) + 0] = ghost_value(s, f, -1, y);
+        f[(size_t)(y + 1) * (nx + 2) + (nx + 1)] = ghost_value(s, f, nx, y);
+    }
+    for (int x = -1; x <= nx; ++x) {
+        f[(size_t)0 * (nx + 2) + (x + 1)] = ghost_value(s, f, x, -1);
+        f[(size_t)(ny + 1) * (nx + 2) + (x + 1)] = ghost_value(s, f, x, ny);
+    }
+}
+
+/* Pass 4: colour field on the domain, then the ghost layer; with the
+ * Navier-Stokes correction also Q^k = (1.8 alpha_k - 0.8) rho_k u of
+ * Sec. 2.1.3, its ghost values by the same rules (R14) */
 static void pass_color_field(or_sim *s)
 {
     int nx = s->p.nx, ny = s->p.ny;
-    size_t n = (size_t)nx * ny;
+    size_t n = (size_t)nx * ny, g = (size_t)(nx + 2) * (ny + 2);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t c = (size_t)y * nx + x;
             s->psi[(size_t)(y + 1) * (nx + 2) + (x + 1)] = color_field(s, s->rho[c], s->rho[n + c]);
         }
-    /* ghost columns first (they only read the domain), then ghost rows */
-    for (int y = 0; y < ny; ++y) {
-        s->psi[(size_t)(y + 1) * (nx + 2) + 0] = psi_ghost(s, -1, y);
-        s->psi[(size_t)(y + 1) * (nx + 2) + (nx + 1)] = psi_ghost(s, nx, y);
+    fill_ghosts(s, s->psi);
+    if (!s->p.ns_correction) return;
+    for (int k = 0; k < 2; ++k) {
+        double a = 1.8 * s->alpha[k] - 0.8;
+        double *qx = s->q + (2 * k) * g, *qy = s->q + (2 * k + 1) * g;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t c = (size_t)y * nx + x;
+                qx[(size_t)(y + 1) * (nx + 2) + (x + 1)] = a * s->rho[k * n + c] * s->ux[c];
+                qy[(size_t)(y + 1) * (nx + 2) + (x + 1)] = a * s->rho[k * n + c] * s->uy[c];
+            }
+        fill_ghosts(s, qx);
+        fill_ghosts(s, qy);
     }
-    for (int x = -1; x <= nx; ++x) {
-        s->psi[(size_t)0 * (nx + 2) + (x + 1)] = psi_ghost(s, x, -1);
-        s->psi[(size_t)(ny + 1) * (nx + 2) + (x + 1)] = psi_ghost(s, x, ny);
-    }
+}
+
+/* dQx/dx and dQy/dy of colour k at (x, y) with the stencil of
+ * eq. (colorGradient) (Sec. 2.1.3) */
+static void q_divergence(const or_sim *s, int k, int x, int y, double *dqx, double *dqy)
+{
+    int nx = s->p.nx, ny = s->p.ny;
+    size_t g = (size_t)(nx + 2) * (ny + 2);
+    double px[9], py[9], Gx[2], Gy[2];
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            size_t o = (size_t)(y + 1 + dy) * (nx + 2) + (x + 1 + dx);
+            px[(dy + 1) * 3 + (dx + 1)] = s->q[(2 * k) * g + o];
+            py[(dy + 1) * 3 + (dx + 1)] = s->q[(2 * k + 1) * g + o];
+        }
+    or_gradient3x3(px, Gx);
+    or_gradient3x3(py, Gy);
+    *dqx = Gx[0];
+    *dqy = Gy[1];
 }
 
 /* Pass 5: per node collision (Sec. 2.1), perturbation (Sec. 2.2),
@@ -595,7 +704,7 @@ static void pass_collide(or_sim *s)
             double Nk[2][9], Ek[2][9], Gk[2][9];
             for (int k = 0; k < 2; ++k) {
                 for (int i = 0; i < 9; ++i) Nk[k][i] = POP(s->strm, k, i, y, x);
-                or_equilibrium(rk[k], u, v, s->alpha[k], Ek[k]);
+                equilibrium(s, rk[k], u, v, k, Ek[k]);
                 for (int i = 0; i < 9; ++i) {
                     /* Guo force density rho_k g (R4) */
                     double cu = CX[i] * u + CY[i] * v;
@@ -607,6 +716,17 @@ static void pass_collide(or_sim *s)
             double Nss[9];
             double pert[9];
             or_perturbation(F, A, pert);
+            /* Navier-Stokes correction source per colour (Sec. 2.1.3, MRT only) */
+            double Uk[2][9] = {{0.0}};
+            if (p->ns_correction && p->collision == OR_MRT) {
+                double s9[9];
+                mrt_rates(w, p->mrt_lambda, s9);
+                for (int k = 0; k < 2; ++k) {
+                    double dqx, dqy;
+                    q_divergence(s, k, x, y, &dqx, &dqy);
+                    or_ns_source(dqx, dqy, s9[1], s9[7], Uk[k]);
+                }
+            }
             if (!p->percolor) {
                 /* colour-blind form (R8) */
                 double N[9], E[9], G[9], Ns[9];
@@ -623,7 +743,7 @@ static void pass_collide(or_sim *s)
                     mrt_rates(w, p->mrt_lambda, s9);
                     for (int j = 0; j < 9; ++j) half[j] = 1.0 - s9[j] / 2.0;
                     mrt_apply(G, half, Gf);
-                    for (int i = 0; i < 9; ++i) Ns[i] += Gf[i];
+                    for (int i = 0; i < 9; ++i) Ns[i] += Gf[i] + Uk[0][i] + Uk[1][i];
                 }
                 for (int i = 0; i < 9; ++i) Nss[i] = Ns[i] + pert[i];
             } else {
@@ -641,7 +761,7 @@ static void pass_collide(or_sim *s)
                         mrt_rates(w, p->mrt_lambda, s9);
                         for (int j = 0; j < 9; ++j) half[j] = 1.0 - s9[j] / 2.0;
                         mrt_apply(Gk[k], half, Gf);
-                        for (int i = 0; i < 9; ++i) Ns[i] += Gf[i];
+                        for (int i = 0; i < 9; ++i) Ns[i] += Gf[i] + Uk[k][i];
                     }
                     for (int i = 0; i < 9; ++i) Nss[i] += Ns[i] + 0.5 * pert[i];
                 }

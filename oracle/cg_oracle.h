@@ -48,6 +48,8 @@ typedef struct {
                                Sec. 2.5 item 1) at y = -1/2 and y = ny - 1/2 */
     double contact_angle;   /* walls: static contact angle of the red fluid, measured through red,
                                in degrees (Sec. 2.4); < 0: no adjustment of the colour gradient */
+    int ns_correction;      /* 1: Sec. 2.1.3 Navier-Stokes correction (Hermite equilibrium everywhere,
+                               the MRT source U^k, Hermite terms of the Zou-He completion) */
 } or_params;
 
 typedef struct or_sim or_sim;
@@ -59,6 +61,9 @@ void   or_alphas(double rho0_r, double rho0_b, double alpha_light, double *alpha
 void   or_equilibrium(double rho_k, double ux, double uy, double alpha_k, double *out9);
 double or_omega_eff(double psi, double omega_r, double omega_b, double delta);
 void   or_gradient3x3(const double *psi9, double *F2);   /* psi9[(dy+1)*3+(dx+1)] */
+void   or_equilibrium_hermite(double rho_k, double ux, double uy, double alpha_k, double *out9);
+/* Sec. 2.1.3: U = M^{-1} C from dQx/dx, dQy/dy and the rates s_1, s_7 */
+void   or_ns_source(double dQxdx, double dQydy, double s1, double s7, double *out9);
 void   or_perturbation(const double *F2, double A, double *out9); /* the added term */
 /* Sec. 2.4: the colour gradient F2 of a fluid node next to a wall with unit
  * normal ns (pointing into the fluid) turned to make the angle theta (radians,
@@ -67,8 +72,10 @@ void   or_perturbation(const double *F2, double A, double *out9); /* the added t
 void   or_wetting(const double *F2, const double *ns2, double theta, double *out2);
 void   or_recolor(const double *Nss9, double rho_r, double rho_b, const double *F2, double beta,
                   double alpha_r, double alpha_b, double *out_r9, double *out_b9);
-double or_zouhe_west(double *N9, double vx, double vy);   /* completes 1,5,8; returns rho */
-double or_zouhe_east(double *N9, double rho, double vy);  /* completes 3,6,7; returns v_x */
+double or_zouhe_west(double *N9, double vx, double vy, double kap);   /* completes 1,5,8; returns rho */
+double or_zouhe_east(double *N9, double rho, double vy, double kap);  /* completes 3,6,7; returns v_x */
+/* kap: 0 with the equilibrium of Sec. 2.1.1; sum_k chi_k (3 c_s,k^2 - 1) with
+ * the Hermite equilibrium of Sec. 2.1.3 (Sec. 2.5 item 3, term H) */
 void   or_mrt_matrices(double *M81, double *Minv81);
 void   or_mrt_collide(const double *N9, const double *Neq9, double omega, double lambda, double *out9);
 

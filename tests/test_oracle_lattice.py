@@ -191,11 +191,11 @@ def test_bubble_symmetry(orc):
     assert np.max(np.abs(m["ux"] - m["uy"].T)) < 1e-15
 
 
-@pytest.mark.parametrize("collision", ["bgk", "mrt"])
-def test_colour_blind_equals_per_colour(orc, collision):
+@pytest.mark.parametrize("collision,nsc", [("bgk", False), ("mrt", False), ("mrt", True)])
+def test_colour_blind_equals_per_colour(orc, collision, nsc):
     rr, rb, ux, uy = W.random_fields(32, 24, seed=11, rho0_r=1.0, rho0_b=5.0, umax=0.02)
     kw = dict(collision=collision, rho0_r=1.0, rho0_b=5.0, tau_r=0.7, tau_b=1.1, A=1e-3,
-              bc_y="walls", gx=1e-5)
+              bc_y="walls", gx=1e-5, ns_correction=nsc)
     a = orc.Sim(32, 24, **kw).init(rr, rb, ux, uy)
     b = orc.Sim(32, 24, percolor=True, **kw).init(rr, rb, ux, uy)
     a.step(100)
@@ -377,3 +377,76 @@ def test_droplet_takes_the_contact_angle(orc, theta):
     measured = _cap_angle((0.5 * (1 + psi)).sum(), (0.5 * (1 + psi[0])).sum())
     assert abs(measured - theta) <= 6.0
     assert np.max(np.abs(psi - psi[:, ::-1])) < 1e-11
+
+
+# ------------------------------------------- Navier-Stokes correction (Sec. 2.1.3)
+# One fluid with alpha = 0.2 (c_s^2 = 0.48), MRT, tau = 0.8, lambda = 0.8, on
+# periodic lattices of wavelength 64.  Chapman-Enskog expansion of the
+# corrected scheme: every third moment of the equilibrium becomes that of a
+# Maxwellian of temperature c_s^2, so shear and normal viscous stresses share
+# nu = c_s^2 (1/omega - 1/2) and a sound wave damps at
+# Gamma = c_s^2 [(1/s_1 - 1/2) + (1/s_7 - 1/2)] k^2 / 2.  The plain scheme has
+# nu = (1/omega - 1/2) / 3.  A printed C_7 = 3 (1 - s_7/2)(dQx/dx + dQy/dy)
+# decays the Taylor-Green vortex at nu = 0.078; C_1 without its factor 3
+# damps the sound wave 19% slower.
+NSC_L, NSC_TAU = 64, 0.8
+
+
+def _nsc_run(orc, rr, ux, uy, steps, every, probe, nsc=True):
+    ny, nx = rr.shape
+    s = orc.Sim(nx, ny, collision="mrt", tau_r=NSC_TAU, tau_b=NSC_TAU, ns_correction=nsc)
+    s.init(rr, np.zeros_like(rr), ux, uy)
+    t, v = [], []
+    for k in range(steps // every + 1):
+        if k:
+            s.step(every)
+        t.append(k * every)
+        v.append(probe(s.moments()))
+    return np.array(t), np.array(v)
+
+
+def _rate(t, v):
+    return -np.polyfit(t, np.log(v), 1)[0]
+
+
+@pytest.mark.parametrize("nsc", [True, False])
+def test_shear_wave_viscosity(orc, nsc):
+    L = NSC_L
+    k = 2 * np.pi / L
+    yc = np.arange(L) + 0.5
+    rr = np.ones((L, 4))
+    ux = 1e-4 * np.sin(k * yc)[:, None] * np.ones((1, 4))
+    t, a = _nsc_run(orc, rr, ux, np.zeros_like(rr), 600, 50,
+                    lambda m: np.sum(m["ux"][:, 0] * np.sin(k * yc)) * 2 / L, nsc)
+    nu = _rate(t, a) / k ** 2
+    want = (0.48 if nsc else 1 / 3) * (NSC_TAU - 0.5)
+    assert nu == pytest.approx(want, rel=2e-3)
+
+
+def test_taylor_green_vortex_viscosity(orc):
+    """Pure normal strain (p_xx, i.e. C_7): kinetic energy ~ exp(-4 nu k^2 t)."""
+    L = NSC_L
+    k = 2 * np.pi / L
+    yy, xx = np.mgrid[0:L, 0:L] + 0.5
+    ux = 1e-4 * np.sin(k * xx) * np.cos(k * yy)
+    uy = -1e-4 * np.cos(k * xx) * np.sin(k * yy)
+    t, e = _nsc_run(orc, np.ones((L, L)), ux, uy, 600, 50, lambda m: np.sum(m["ux"] ** 2 + m["uy"] ** 2))
+    assert _rate(t, e) / (4 * k ** 2) == pytest.approx(0.48 * (NSC_TAU - 0.5), rel=5e-3)
+
+
+def test_sound_wave_damping(orc):
+    """Standing sound wave (trace of the stress, i.e. C_1, with C_7): the
+    acoustic energy c_s^2 rho'^2 + u'^2 of the mode decays at 2 Gamma."""
+    L = NSC_L
+    k = 2 * np.pi / L
+    xc = np.arange(L) + 0.5
+    rr = (1 + 1e-4 * np.cos(k * xc))[None, :] * np.ones((2, 1))
+
+    def energy(m):
+        ra = np.sum((m["rho_r"][0] - 1) * np.cos(k * xc)) * 2 / L
+        ua = np.sum(m["ux"][0] * np.sin(k * xc)) * 2 / L
+        return 0.48 * ra ** 2 + ua ** 2
+    t, e = _nsc_run(orc, rr, np.zeros_like(rr), np.zeros_like(rr), 3000, 10, energy)
+    w = 1 / NSC_TAU
+    gamma = 0.48 * ((1 / (0.8 * w) - 0.5) + (1 / w - 0.5)) * k ** 2 / 2
+    assert _rate(t, e) / 2 == pytest.approx(gamma, rel=5e-3)

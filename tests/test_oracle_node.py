@@ -263,3 +263,64 @@ def test_wetting_end_angles(orc):
         F = np.array(F)
         assert np.allclose(orc.wetting(F, ns, 0.0), np.linalg.norm(F) * ns, atol=1e-15)
         assert np.allclose(orc.wetting(F, ns, np.pi), -np.linalg.norm(F) * ns, atol=1e-15)
+
+
+# ------------------------------------------- Navier-Stokes correction (Sec. 2.1.3)
+@pytest.mark.parametrize("alpha", [0.2, 0.6, 0.95])
+def test_hermite_equilibrium_moments(orc, alpha):
+    """The Hermite equilibrium keeps mass, momentum and the momentum flux
+    rho c_s^2 I + rho u u of the plain one; its mixed third moments become
+    c_s^2 rho u (those of a Maxwellian of temperature c_s^2) while
+    sum c_x^3 N^e = rho u_x stays (c_x^3 = c_x on the lattice).  A garbled
+    (3 c_i - 4) read any other way breaks one of these."""
+    cx, cy, _, _ = orc.lattice()
+    cs2 = 3 * (1 - alpha) / 5
+    for _ in range(10):
+        rho = RNG.uniform(0.5, 2)
+        ux, uy = RNG.uniform(-0.05, 0.05, 2)
+        H = orc.equilibrium_hermite(rho, ux, uy, alpha)
+        E = orc.equilibrium(rho, ux, uy, alpha)
+        assert H.sum() == pytest.approx(rho, rel=1e-14)
+        assert H @ cx == pytest.approx(rho * ux, abs=1e-15)
+        assert H @ cy == pytest.approx(rho * uy, abs=1e-15)
+        for a, b in ((cx * cx, None), (cy * cy, None), (cx * cy, None)):
+            assert H @ a == pytest.approx(E @ a, abs=1e-15)
+        assert H @ (cx * cx) == pytest.approx(rho * cs2 + rho * ux * ux, abs=1e-14)
+        assert H @ (cx * cy) == pytest.approx(rho * ux * uy, abs=1e-15)
+        assert H @ (cx * cx * cy) == pytest.approx(cs2 * rho * uy, abs=1e-15)
+        assert H @ (cx * cy * cy) == pytest.approx(cs2 * rho * ux, abs=1e-15)
+        assert H @ (cx ** 3) == pytest.approx(rho * ux, abs=1e-15)
+    # c_s^2 = 1/3 (alpha = 4/9): the correction factor is 1, the forms agree
+    assert np.allclose(orc.equilibrium_hermite(1.3, 0.02, -0.01, 4 / 9),
+                       orc.equilibrium(1.3, 0.02, -0.01, 4 / 9), atol=1e-16)
+
+
+def test_ns_source_conserves(orc):
+    """U = M^-1 C with C in the moments e and p_xx only: no mass, no momentum."""
+    cx, cy, _, _ = orc.lattice()
+    for _ in range(10):
+        U = orc.ns_source(*RNG.uniform(-1e-3, 1e-3, 2), *RNG.uniform(0.2, 1.9, 2))
+        assert abs(U.sum()) < 1e-18 and abs(U @ cx) < 1e-18 and abs(U @ cy) < 1e-18
+    assert np.all(orc.ns_source(0.0, 0.0, 1.0, 1.2) == 0.0)
+
+
+@pytest.mark.parametrize("alphas", [(0.2, 0.2), (0.2, 0.92), (0.6, 0.2)])
+def test_zouhe_hermite_exact_on_equilibrium(orc, alphas):
+    """With the Hermite equilibrium and its term H (kap = sum chi_k (3 c_s,k^2 - 1)),
+    a two-colour equilibrium state is completed exactly; without H it is not."""
+    for _ in range(10):
+        rho = RNG.uniform(0.5, 2)
+        chi = RNG.uniform(0, 1)
+        ux, uy = RNG.uniform(-0.05, 0.05, 2)
+        E = (orc.equilibrium_hermite(chi * rho, ux, uy, alphas[0])
+             + orc.equilibrium_hermite((1 - chi) * rho, ux, uy, alphas[1]))
+        kap = sum(c * (3 * 3 * (1 - a) / 5 - 1) for c, a in zip((chi, 1 - chi), alphas))
+        rho_w, Nw = orc.zouhe_west(np.where(np.isin(np.arange(9), [1, 5, 8]), 0.0, E), ux, uy, kap)
+        assert rho_w == pytest.approx(rho, rel=1e-13)
+        assert np.allclose(Nw, E, atol=1e-14)
+        vx, Ne = orc.zouhe_east(np.where(np.isin(np.arange(9), [3, 6, 7]), 0.0, E), rho, uy, kap)
+        assert vx == pytest.approx(ux, abs=1e-14)
+        assert np.allclose(Ne, E, atol=1e-14)
+        if abs(kap * ux) > 1e-4:
+            _, N0 = orc.zouhe_west(np.where(np.isin(np.arange(9), [1, 5, 8]), 0.0, E), ux, uy, 0.0)
+            assert not np.allclose(N0, E, atol=1e-8)
