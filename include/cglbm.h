@@ -94,6 +94,19 @@ typedef struct {
     int32_t wetting;         /* 0 or 1                                                   */
     int32_t reserved0;       /* must be 0                                                */
     double contact_angle;    /* degrees, 0 <= contact_angle <= 180                       */
+    /* Navier-Stokes correction (Sec. 2.1.3; MRT only): ns_correction = 1 uses
+     * the third-order Hermite equilibrium (its factor (3 c_i - 4) read as
+     * (3 |c_i|^2 - 4)) in the collision, the initialisation and the Zou-He
+     * completion (term H of Sec. 2.5 item 3), and adds the MRT source
+     * M^-1 C with C_1 = 3 (1 - s_1/2)(dQx/dx + dQy/dy) and
+     * C_7 = (1 - s_7/2)(dQx/dx - dQy/dy) (printed with a factor 3, omega_eff
+     * and a plus sign; this form follows from row 7 of M, c_x^2 - c_y^2),
+     * Q = sum_k (1.8 alpha_k - 0.8) rho_k u differentiated with the stencil
+     * of eq. (colorGradient) (ghost values beyond walls and open faces as for
+     * the colour field).  The kinematic viscosity of fluid k is then
+     * c_s,k^2 (tau_k - 1/2) instead of (tau_k - 1/2) / 3. */
+    int32_t ns_correction;   /* 0 or 1                                                   */
+    int32_t reserved1;       /* must be 0                                                */
 } lbm_params;
 
 typedef struct {

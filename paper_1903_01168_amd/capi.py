@@ -41,6 +41,7 @@ class LbmParams(C.Structure):
         ("gx", C.c_double), ("gy", C.c_double),
         ("u_in_r", C.c_double), ("u_in_b", C.c_double), ("p_out", C.c_double),
         ("wetting", C.c_int32), ("reserved0", C.c_int32), ("contact_angle", C.c_double),
+        ("ns_correction", C.c_int32), ("reserved1", C.c_int32),
     ]
 
 
@@ -127,7 +128,8 @@ def make_params(p: dict) -> LbmParams:
         tau_r=p["tau_r"], tau_b=p["tau_b"], delta=p["delta"], A=p["A"], sigma=p["sigma"],
         beta=p["beta"], mrt_lambda=p["mrt_lambda"], gx=p["gx"], gy=p["gy"],
         u_in_r=p["u_in_r"], u_in_b=p["u_in_b"], p_out=p["p_out"],
-        wetting=1 if ca >= 0 else 0, contact_angle=ca if ca >= 0 else 0.0)
+        wetting=1 if ca >= 0 else 0, contact_angle=ca if ca >= 0 else 0.0,
+        ns_correction=int(bool(p.get("ns_correction", False))))
 
 
 def _f64(a, shape):

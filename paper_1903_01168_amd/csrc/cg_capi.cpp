@@ -103,6 +103,12 @@ int validate(const lbm_params *p, std::string &msg)
     if (p->wetting && !(p->contact_angle >= 0 && p->contact_angle <= 180)) {
         msg = "contact_angle must be in [0, 180] degrees"; return LBM_E_INVAL;
     }
+    if ((p->ns_correction != 0 && p->ns_correction != 1) || p->reserved1 != 0) {
+        msg = "ns_correction must be 0 or 1 and reserved1 0"; return LBM_E_INVAL;
+    }
+    if (p->ns_correction && p->collision != LBM_COLL_MRT) {
+        msg = "the Navier-Stokes correction needs MRT collision"; return LBM_E_INVAL;
+    }
     return LBM_OK;
 }
 
@@ -179,6 +185,8 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
     if (p->sigma > 0) f |= cgd::F_SIGMA;
     if (p->gx != 0.0 || p->gy != 0.0) f |= cgd::F_FORCE;
     if (p->wetting) f |= cgd::F_WET;
+    if (p->ns_correction) f |= cgd::F_NSC;
+    for (int k = 0; k < 2; ++k) d.k3[k] = (float)(0.8 - 1.8 * alpha[k]);   // 3 c_s,k^2 - 1
     d.flags = f;
     // wetting (Sec. 2.4): the gradient makes the angle 180 - contact_angle
     // with the wall normal; its cosine and sine, exact at 0 and 180 degrees
@@ -236,6 +244,21 @@ std::vector<int> cache_groups(const std::vector<size_t> &bytes)
         }
     }
     first.push_back(n);
+    return first;
+}
+
+std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind)
+{
+    std::vector<int> first(1, 0);
+    const int n = (int)bytes.size();
+    for (int a = 0; a < n;) {
+        int e = a + 1;
+        while (e < n && kind[e] == kind[a]) ++e;
+        const std::vector<int> f = cache_groups(std::vector<size_t>(bytes.begin() + a, bytes.begin() + e));
+        for (size_t j = 1; j < f.size(); ++j) first.push_back(a + f[j]);
+        a = e;
+    }
+    if (n == 0) first.push_back(0);
     return first;
 }
 
@@ -468,7 +491,8 @@ static int build_graph(lbm_ctx *c, int parity)
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
     hipError_t le = hipSuccess;
     for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
-        le = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (parity + j) & 1, 0, c->cap_stream);
+        le = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (parity + j) & 1, 0, c->cap_stream,
+                              c->p.ns_correction != 0);
     e = hipStreamEndCapture(c->cap_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -500,7 +524,8 @@ int lbm_step(lbm_ctx *c, int64_t n)
         n -= kGraphSteps;
     }
     for (; n > 0; --n) {
-        hipError_t e = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (int)(c->steps & 1), 0, c->stream);
+        hipError_t e = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (int)(c->steps & 1), 0, c->stream,
+                                        c->p.ns_correction != 0);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->steps++;
     }
@@ -680,6 +705,7 @@ struct BatchGroup {
     std::vector<SlotDesc> slots;
     SlotDesc *d_slots = nullptr;
     int tiles = 0;
+    bool nsc = false;                   // some lattice carries the Navier-Stokes correction
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
@@ -744,8 +770,12 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
     }
     b->tx = tx;
     std::vector<size_t> bytes;
-    for (int i = 0; i < n; ++i) bytes.push_back(2 * ctxs[i]->buf_bytes);
-    const std::vector<int> first = cache_groups(bytes);
+    std::vector<char> kind;
+    for (int i = 0; i < n; ++i) {
+        bytes.push_back(2 * ctxs[i]->buf_bytes);
+        kind.push_back(ctxs[i]->p.ns_correction != 0);
+    }
+    const std::vector<int> first = cache_groups(bytes, kind);
     b->groups.resize(first.size() - 1);
     for (size_t gi = 0; gi + 1 < first.size(); ++gi) {
         BatchGroup &G = b->groups[gi];
@@ -761,6 +791,7 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
             if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer
             tiles += (long long)d.tiles_x * d.tiles_y;
             G.slots.push_back(d);
+            if (d.flags & cgd::F_NSC) G.nsc = true;
         }
         if (tiles > INT_MAX / 2) {
             lbm_batch_destroy(b);
@@ -806,7 +837,7 @@ static int batch_graph(lbm_batch *b, BatchGroup &G, int parity)
     hipError_t le = hipSuccess;
     for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
         le = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (parity + j) & 1, 0,
-                              b->cap_stream);
+                              b->cap_stream, G.nsc);
     e = hipStreamEndCapture(b->cap_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -839,7 +870,7 @@ static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n)
     }
     for (; n > 0; --n, ++t) {
         hipError_t e = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (int)(t & 1), 0,
-                                        b->stream);
+                                        b->stream, G.nsc);
         if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     }
     return LBM_OK;

@@ -26,6 +26,8 @@ __host__ __device__ constexpr int vclass(int i) { return i == 0 ? 0 : (i <= 4 ? 
 // D2Q9 weights W (Sec. 2.1.1) and perturbation coefficients B (Sec. 2.2) by class
 __host__ __device__ constexpr float wgt(int i) { return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f); }
 __host__ __device__ constexpr float bco(int i) { return i == 0 ? -4.0f / 27.0f : (i <= 4 ? 2.0f / 27.0f : 5.0f / 108.0f); }
+// (3 |c_i|^2 - 4) / 2: the third-order factor of the Hermite equilibrium (Sec. 2.1.3)
+__host__ __device__ constexpr float hco(int i) { return i == 0 ? -2.0f : (i <= 4 ? -0.5f : 1.0f); }
 
 // the direction with the same c_x and the opposite c_y (free-slip reflection)
 __host__ __device__ constexpr int mirror_y(int i)
@@ -39,7 +41,7 @@ static_assert(cx(mirror_y(5)) == cx(5) && cy(mirror_y(5)) == -cy(5) && cx(mirror
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
 
 enum : int { F_XPER = 1, F_XOPEN = 2, F_YPER = 4, F_MRT = 8, F_SIGMA = 16, F_FORCE = 32, F_SLIP_LO = 64,
-             F_SLIP_HI = 128, F_WET = 256 };
+             F_SLIP_HI = 128, F_WET = 256, F_NSC = 512 };
 enum : int { ST_F32 = 0, ST_F16S = 1, ST_BF16S = 2 };
 
 // ------------------------------------------------------------- descriptor --
@@ -73,6 +75,8 @@ struct SlotDesc {
     // wetting (F_WET): cosine and sine of the angle between the adjusted
     // colour gradient and the wall normal (180 degrees - contact angle)
     float wet_c, wet_s;
+    // Navier-Stokes correction (F_NSC): 3 c_s,k^2 - 1 = 0.8 - 1.8 alpha_k
+    float k3[2];
 };
 
 // ------------------------------------------------------------------ codec --
@@ -497,9 +501,12 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
         const float vx = red ? S.u_in[0] : S.u_in[1];
         float *N = nd.n;
         const float rin = (N[0] + N[2] + N[4] + 2.f * (N[3] + N[6] + N[7])) / (1.f - vx);
-        N[1] = N[3] + (2.f / 3.f) * rin * vx;
-        N[5] = N[7] - 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f);
-        N[8] = N[6] + 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f);
+        // Hermite equilibrium (Sec. 2.1.3): the corrective term H of Sec. 2.5
+        // item 3, with the prescribed colour's 3 c_s^2 - 1
+        const float H = (S.flags & F_NSC) ? (red ? S.k3[0] : S.k3[1]) * rin * vx * (1.f / 3.f) : 0.f;
+        N[1] = N[3] + (2.f / 3.f) * rin * vx - H;
+        N[5] = N[7] - 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f) + 0.5f * H;
+        N[8] = N[6] + 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f) + 0.5f * H;
         nd.rr = red ? rin : 0.f;
         nd.rb = red ? 0.f : rin;
     } else if (xc.outlet) {
@@ -510,9 +517,10 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
         const float rho_o = nd.rr + nd.rb;
         float *N = nd.n;
         const float vx = (N[0] + N[2] + N[4] + 2.f * (N[1] + N[5] + N[8])) / rho_o - 1.f;
-        N[3] = N[1] - (2.f / 3.f) * rho_o * vx;
-        N[6] = N[8] - 0.5f * (N[2] - N[4]) - rho_o * vx * (1.f / 6.f);
-        N[7] = N[5] + 0.5f * (N[2] - N[4]) - rho_o * vx * (1.f / 6.f);
+        const float H = (S.flags & F_NSC) ? (chir * S.k3[0] + chib * S.k3[1]) * rho_o * vx * (1.f / 3.f) : 0.f;
+        N[3] = N[1] - (2.f / 3.f) * rho_o * vx + H;
+        N[6] = N[8] - 0.5f * (N[2] - N[4]) - rho_o * vx * (1.f / 6.f) - 0.5f * H;
+        N[7] = N[5] + 0.5f * (N[2] - N[4]) - rho_o * vx * (1.f / 6.f) - 0.5f * H;
     }
     if (xc.inlet || xc.outlet) {          // an open boundary prescribes the colour densities
         rho[0] = (double)nd.rr;
@@ -750,8 +758,13 @@ __device__ __forceinline__ void wet(const SlotDesc &S, bool bottom, float &Fx, f
 // Collision (Sec. 2.1.1 BGK / Sec. 2.1.2 MRT, colour-blind), perturbation
 // (Sec. 2.2) and recolouring (Sec. 2.3) of one node.  F = colour gradient,
 // psi = own colour field.  Output: red and blue post-recolouring populations.
+// NSC (compiled in) with nsc (the lattice's flag): the Navier-Stokes
+// correction of Sec. 2.1.3, i.e. the Hermite equilibrium and the MRT source
+// M^-1 C from dqx = dQx/dx, dqy = dQy/dy of Q = sum_k (1.8 alpha_k - 0.8) rho_k u.
+template <bool NSC = false>
 __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float psi, float Fx, float Fy,
-                                        float *outr, float *outb)
+                                        float *outr, float *outb, bool nsc = false, float dqx = 0.f,
+                                        float dqy = 0.f)
 {
     const float rr = nd.rr, rb = nd.rb;
     const float rho = rr + rb;
@@ -764,6 +777,11 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
     float G[9];       // Guo forcing source (force density rho g)
     const bool force = S.flags & F_FORCE;
     const float gxr = rho * S.gx, gyr = rho * S.gy;
+    // Hermite equilibrium: the linear term of colour k carries the factor
+    // 1 + (3 c_s,k^2 - 1)(3 |c_i|^2 - 4) / 2; summed over the colours its
+    // density is rho + hco(i) K with K = sum_k rho_k (3 c_s,k^2 - 1)
+    const bool herm = NSC && nsc;
+    const float K = herm ? rr * S.k3[0] + rb * S.k3[1] : 0.f;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const float cu = cx(i) * ux + cy(i) * uy;
@@ -774,7 +792,10 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
         t = __builtin_fmaf(-rb, S.phi[1][c], t);
         // unit mass of the FP32 rest weights, and the exact mass of the node
         if (i == 0) t -= rr * S.phi0_eps[0] + rb * S.phi0_eps[1] + nd.dm;
-        neq[i] = t - rho * wgt(i) * (3.f * cu + 4.5f * cu * cu - 1.5f * uu);
+        if (herm && i != 0)
+            neq[i] = t - wgt(i) * (3.f * cu * __builtin_fmaf(hco(i), K, rho) + rho * (4.5f * cu * cu - 1.5f * uu));
+        else
+            neq[i] = t - rho * wgt(i) * (3.f * cu + 4.5f * cu * cu - 1.5f * uu);
         G[i] = force ? wgt(i) * ((3.f * (cx(i) - ux) + 9.f * cu * cx(i)) * gxr +
                                  (3.f * (cy(i) - uy) + 9.f * cu * cy(i)) * gyr)
                      : 0.f;
@@ -789,6 +810,12 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
         for (int j = 0; j < 9; ++j) {
             const float s = (j >= 7) ? w : sl;
             q[j] = s * m[j] - (force ? (1.f - 0.5f * s) * mg[j] : 0.f);
+        }
+        if (herm) {
+            // source U = M^-1 C, C_1 = 3 (1 - s_1/2)(dQx/dx + dQy/dy),
+            // C_7 = (1 - s_7/2)(dQx/dx - dQy/dy): N* = N - M^-1 (q - C)
+            q[1] -= 3.f * (1.f - 0.5f * sl) * (dqx + dqy);
+            q[7] -= (1.f - 0.5f * w) * (dqx - dqy);
         }
         float dn[9];
         mrt_inv(q, dn);

@@ -61,7 +61,7 @@ constexpr int kOut = 60;
 // of the rows y-1, y, y+1 lives in registers, horizontal neighbours come from
 // the adjacent lanes, and the populations of row y+2 are requested before row
 // y collides.
-template <int ST, int W>
+template <int ST, int W, bool NSC>
 __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
                                                  int parity, int launch_idx)
 {
@@ -106,6 +106,41 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
     auto real_row = [&](int r) { return yper ? wrapi(r, ny) : r; };
     auto gathered = [&](int r) { return yper || (r >= 0 && r < ny); };
 
+    // Navier-Stokes correction (Sec. 2.1.3): Q = sum_k (1.8 alpha_k - 0.8)
+    // rho_k u per node, and per row the two partial sums its stencil needs:
+    // d = Q_x(east) - Q_x(west) and s = Q_y / 3 + (Q_y(east) + Q_y(west)) / 12,
+    // so that dQx/dx = d(y) / 3 + (d(y-1) + d(y+1)) / 12 and
+    // dQy/dy = s(y+1) - s(y-1) (the stencil of eq. (colorGradient)).  Ghost
+    // rows beyond a wall take the colour field's extrapolation of Q.
+    const bool nsc = NSC && (S.flags & F_NSC);
+    struct QRow {
+        float d, s;
+    };
+    auto qrow = [&](float qx, float qy) -> QRow {
+        return QRow{from_east(qx) - from_west(qx), (1.f / 3.f) * qy + (1.f / 12.f) * (from_east(qy) + from_west(qy))};
+    };
+    auto qnode = [&](const Node &nd, float &qx, float &qy) {
+        float ux, uy;
+        velocity(S, nd, nd.rr + nd.rb, ux, uy);
+        const float a = -(nd.rr * S.k3[0] + nd.rb * S.k3[1]);
+        qx = a * ux;
+        qy = a * uy;
+    };
+    auto qreal = [&](const Node &nd) -> QRow {
+        float qx, qy;
+        qnode(nd, qx, qy);
+        return qrow(qx, qy);
+    };
+    auto qghost = [&](const Node &adj) -> QRow {
+        float qx, qy;
+        qnode(adj, qx, qy);
+        // the neighbour values are fetched by every lane before any lane
+        // selects: a cross-lane read under a lane condition would see the
+        // inactive lanes as zero
+        const Psi3 fx = psi3(qx), fy = psi3(qy);
+        return qrow(ghost(fx).c, ghost(fy).c);
+    };
+
     // Even strips march up, odd strips march down: the two strips on either
     // side of a strip boundary then read their shared halo rows at the same
     // time (both at the start or both at the end), so the second read hits L2.
@@ -115,6 +150,7 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
 
     // prologue: the row behind the first one, and the first one
     Psi3 pb, p0;                               // colour field of rows y-d and y
+    QRow qb{}, q0{};                           // Q partial sums of rows y-d and y (NSC)
     Node cur;
     {
         const bool have_b = gathered(ys - d);
@@ -126,10 +162,15 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
         if (have_b) {
             const Node t = finish<ST>(S, rb, xc, rwb);
             pb = psi3(color_field(S, t.rr, t.rb));
+            if (nsc) qb = qreal(t);
         }
         cur = finish<ST>(S, r0, xc, rw0);
         p0 = psi3(color_field(S, cur.rr, cur.rb));
-        if (!have_b) pb = ghost(p0);           // the row behind lies beyond a wall
+        if (nsc) q0 = qreal(cur);
+        if (!have_b) {                         // the row behind lies beyond a wall
+            pb = ghost(p0);
+            if (nsc) qb = qghost(cur);
+        }
     }
     bool have_p = gathered(ys + d);
     RowSrc rwp = make_row<ST>(S, have_p ? real_row(ys + d) : ys);
@@ -141,11 +182,14 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
     for (int y = ys; y != ye; y += d) {
         Node nxt;
         Psi3 pa;                               // colour field of row y+d (ahead)
+        QRow qa{};
         if (have_p) {
             nxt = finish<ST>(S, pend, xc, rwp);
             pa = psi3(color_field(S, nxt.rr, nxt.rb));
+            if (nsc) qa = qreal(nxt);
         } else {
             pa = ghost(p0);                    // row y+d lies beyond a wall
+            if (nsc) qa = qghost(cur);
         }
         // request row y+2d now; it arrives while row y collides
         const int r2 = y + 2 * d;
@@ -161,12 +205,20 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
             float Fy = fd * ((1.f / 3.f) * (pa.c - pb.c) + (1.f / 12.f) * ((pa.e + pa.w) - (pb.e + pb.w)));
             if ((S.flags & F_WET) && (y == 0 || y == ny - 1)) wet(S, y == 0, Fx, Fy);
             float outr[9], outb[9];
-            collide(S, cur, p0.c, Fx, Fy, outr, outb);
+            if constexpr (NSC) {
+                const float dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
+                const float dqy = fd * (qa.s - qb.s);
+                collide<true>(S, cur, p0.c, Fx, Fy, outr, outb, nsc, dqx, dqy);
+            } else {
+                collide(S, cur, p0.c, Fx, Fy, outr, outb);
+            }
             if (ST == ST_F32) conserve(cur, outr, outb);   // 16-bit storage rounds far coarser
             store18<ST>(S, dst, xc.o0, (uint32_t)y * rowbytes, outr, outb, cur.mr, cur.mb);
         }
         pb = p0;
         p0 = pa;
+        qb = q0;
+        q0 = qa;
         cur = nxt;
     }
 }
@@ -191,8 +243,10 @@ __global__ void __launch_bounds__(256) k_init(const SlotDesc *__restrict__ sd, c
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const float cu = cx(i) * ux + cy(i) * uy;
-                // Sec. 2.1.1 eq. (equilibrium)
-                e[k][i] = rk[k] * (S.phi[k][vclass(i)] + wgt(i) * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+                // Sec. 2.1.1 eq. (equilibrium), or with the Navier-Stokes
+                // correction Sec. 2.1.3 eq. (equilibrium_hermite)
+                const float lin = (S.flags & F_NSC) ? 3.f * cu * (1.f + hco(i) * S.k3[k]) : 3.f * cu;
+                e[k][i] = rk[k] * (S.phi[k][vclass(i)] + wgt(i) * (lin + 4.5f * cu * cu - 1.5f * uu));
                 if (i == 0) e[k][i] += rk[k] * S.phi0_eps[k];
             }
         store18<ST>(S, dst, (uint32_t)x * Codec<ST>::bytes, (uint32_t)y * S.pitch * Codec<ST>::bytes, e[0], e[1],
@@ -356,25 +410,28 @@ __global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uin
 }
 
 // ------------------------------------------------------------- launchers --
-template <int ST>
+template <int ST, bool NSC>
 static hipError_t step_st(int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx, hipStream_t s)
 {
     switch (tx) {
-    case 64: hipLaunchKernelGGL((k_step<ST, 1>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
-    case 128: hipLaunchKernelGGL((k_step<ST, 2>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
-    case 256: hipLaunchKernelGGL((k_step<ST, 4>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
+    case 64: hipLaunchKernelGGL((k_step<ST, 1, NSC>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
+    case 128: hipLaunchKernelGGL((k_step<ST, 2, NSC>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
+    case 256: hipLaunchKernelGGL((k_step<ST, 4, NSC>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_step(int storage, int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx,
-                       hipStream_t s)
+                       hipStream_t s, bool nsc)
 {
     switch (storage) {
-    case ST_F32: return step_st<ST_F32>(tx, d, nslots, tiles, parity, idx, s);
-    case ST_F16S: return step_st<ST_F16S>(tx, d, nslots, tiles, parity, idx, s);
-    case ST_BF16S: return step_st<ST_BF16S>(tx, d, nslots, tiles, parity, idx, s);
+    case ST_F32: return nsc ? step_st<ST_F32, true>(tx, d, nslots, tiles, parity, idx, s)
+                            : step_st<ST_F32, false>(tx, d, nslots, tiles, parity, idx, s);
+    case ST_F16S: return nsc ? step_st<ST_F16S, true>(tx, d, nslots, tiles, parity, idx, s)
+                             : step_st<ST_F16S, false>(tx, d, nslots, tiles, parity, idx, s);
+    case ST_BF16S: return nsc ? step_st<ST_BF16S, true>(tx, d, nslots, tiles, parity, idx, s)
+                              : step_st<ST_BF16S, false>(tx, d, nslots, tiles, parity, idx, s);
     }
     return hipErrorInvalidValue;
 }

@@ -5,8 +5,11 @@
 
 namespace cgd {
 
+// nsc: launch the variant that carries the Navier-Stokes correction (Sec.
+// 2.1.3); it applies the correction to the lattices whose descriptor has
+// F_NSC and steps the others as the plain variant does
 hipError_t launch_step(int storage, int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx,
-                       hipStream_t s);
+                       hipStream_t s, bool nsc);
 hipError_t launch_init(int storage, const SlotDesc *d, long long nodes, const float *fields, int which,
                        hipStream_t s);
 int moments_blocks(long long nodes);

@@ -64,6 +64,7 @@ def test_layout_sizes(lib):
     dict(bc_x="open", p_out=0.0), dict(bc_x="open", nx=1, p_out=0.48),
     dict(bc_x="open", p_out=0.48, u_in_r=1.5),
     dict(contact_angle=60.0), dict(bc_y="walls", contact_angle=181.0),
+    dict(ns_correction=True),                         # the correction is an MRT source
 ])
 def test_validation_rejects(lib, bad):
     kw = dict(nx=16, ny=8, A=1e-3)
@@ -75,7 +76,9 @@ def test_validation_accepts(lib):
     for kw in (dict(), dict(bc_x="open", p_out=0.48), dict(bc_y="walls", gx=1e-6), dict(bc_y="freeslip"),
                dict(bc_y="slip_top", bc_x="open", p_out=0.48), dict(collision="mrt"), dict(storage="bf16s"),
                dict(A=0.0, sigma=1e-3), dict(bc_y="walls", contact_angle=60.0),
-               dict(bc_y="slip_top", contact_angle=0.0), dict(bc_y="freeslip", contact_angle=180.0)):
+               dict(bc_y="slip_top", contact_angle=0.0), dict(bc_y="freeslip", contact_angle=180.0),
+               dict(collision="mrt", ns_correction=True),
+               dict(collision="mrt", ns_correction=True, bc_x="open", p_out=0.48, bc_y="walls")):
         base = dict(nx=16, ny=8, A=1e-3)
         base.update(kw)
         assert _bytes(W.params(**base)) > 0
@@ -111,4 +114,13 @@ def test_wetting_fields_validated(lib):
     cp.wetting = 2
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
     cp.wetting, cp.reserved0 = 1, 7
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+
+
+def test_ns_correction_fields_validated(lib):
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3, collision="mrt", ns_correction=True))
+    assert cp.ns_correction == 1 and lib.lbm_bytes_required(C.byref(cp)) > 0
+    cp.ns_correction = 2
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp.ns_correction, cp.reserved1 = 1, 1
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
