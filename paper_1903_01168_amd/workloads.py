@@ -18,6 +18,8 @@ available; the paper's sizes and parameters are quoted where they exist):
   heavy/light slugs (Sec. 5.1 periodic case).
 * ``inlet_outlet``   -- channel with a velocity inlet, pressure outlet and
   free-slip walls, stratified two-phase inflow (Sec. 5.2 open channel).
+* ``square_droplet`` -- a square of light fluid relaxing to a circle (Sec. 4
+  square-to-droplet Laplace test).
 * ``wall_droplet``   -- a rectangular droplet on a wall relaxing to a
   prescribed contact angle (Sec. 2.4; the paper's contact-angle case).
 * ``serve_trace``    -- a seeded mix of bubble and slug solve requests.
@@ -211,6 +213,28 @@ def inlet_outlet(seed=0, nx=8192, ny=512, gamma=5, u_in=0.01, A=1e-3, beta=0.7, 
     return dict(name=f"inlet-outlet {nx}x{ny} gamma={gamma} {visc} stratified", params=p,
                 rho_r=rr, rho_b=rb, ux=None, uy=None,
                 inlet_color=np.where(heavy, 1, -1).astype(np.int8))
+
+
+def square_droplet(n, gamma=1.0, M=1.0, sigma=0.01, tau_light=1.0, beta60=0.99, storage="f32",
+                   collision="bgk"):
+    """Square-to-droplet case (Sec. 4 static bubble tests): an n x n periodic
+    lattice, a light square of side round(0.33 n) (red) centred in the heavy
+    fluid (blue), density ratio gamma = rho_heavy / rho_light and dynamic
+    viscosity ratio M = mu_heavy / mu_light, surface tension sigma (0.01 in
+    the paper), beta scaled with the resolution as beta60 (60 / n)^(5/8).
+    The paper does not give tau; the light fluid's is tau_light, the heavy
+    fluid's follows from nu_heavy / nu_light = M / gamma."""
+    a = int(round(0.33 * n))
+    lo = (n - a) // 2
+    red = np.zeros((n, n))
+    red[lo:lo + a, lo:lo + a] = 1.0
+    nu_l = nu_from_tau(tau_light)
+    tau_h = tau_from_nu(nu_l * M / gamma)
+    p = params(nx=n, ny=n, rho0_r=1.0, rho0_b=float(gamma), tau_r=tau_light, tau_b=tau_h, sigma=sigma,
+               beta=beta60 * (60.0 / n) ** 0.625, storage=storage, collision=collision)
+    return dict(name=f"square {n}x{n} gamma={gamma:g} M={M:g}", params=p, rho_r=red,
+                rho_b=float(gamma) * (1.0 - red), ux=None, uy=None, side=a, center=(n / 2, n / 2),
+                gamma=gamma, M=M)
 
 
 def wall_droplet(contact_angle, n=100, sigma=0.01, tau=1.0, beta=0.7, bc_y="walls", storage="f32",
