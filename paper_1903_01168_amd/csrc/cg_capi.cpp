@@ -219,8 +219,14 @@ int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req)
     // 8192 x 512 channel and the nine-lattice 512^2 sweep: FP32 runs best with
     // 4-row strips on wide lattices and 8 on narrow ones (512 columns, 9
     // wavefront tiles), 16-bit storage with 4 rows up to 3M nodes and 8 beyond.
+    // Between 1M and 3M nodes 6-row strips make 0.7 to 2 times as many
+    // wavefronts as the chip holds at once (256 CUs x 4 SIMDs x 4 waves at the
+    // step kernel's register count): there they beat 2-4 rows by 1.4-9% in
+    // both storages (slug, sweep groups) while neither filling the chip too
+    // thinly nor leaving a short last wave.
     int s;
     if (nodes <= (1LL << 17)) s = 1;
+    else if (nodes >= 1000000LL && nodes <= 3000000LL) s = 6;
     else if (nodes <= 1500000LL) s = 2;
     else if (storage == LBM_STORE_F32) s = tiles_x >= 16 ? 4 : 8;
     else s = nodes <= 3000000LL ? 4 : 8;
