@@ -144,9 +144,9 @@ L, TAU = 64, 0.8
 K = 2 * np.pi / L
 
 
-def _decay(rr, ux, uy, steps, every, probe):
+def _decay(rr, ux, uy, steps, every, probe, storage="f32"):
     ny, nx = rr.shape
-    p = W.params(nx=nx, ny=ny, collision="mrt", tau_r=TAU, tau_b=TAU, ns_correction=True)
+    p = W.params(nx=nx, ny=ny, collision="mrt", tau_r=TAU, tau_b=TAU, ns_correction=True, storage=storage)
     t, v = [], []
     with capi.Lattice(p) as g:
         g.init(rr, np.zeros_like(rr), ux, uy)
@@ -158,22 +158,24 @@ def _decay(rr, ux, uy, steps, every, probe):
     return -np.polyfit(np.array(t), np.log(np.array(v)), 1)[0]
 
 
-def test_shear_wave_and_taylor_green():
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_shear_wave_and_taylor_green(storage):
     yc = np.arange(L) + 0.5
     rr = np.ones((L, 4))
     ux = 1e-3 * np.sin(K * yc)[:, None] * np.ones((1, 4))
     nu = _decay(rr, ux, np.zeros_like(rr), 600, 50,
-                lambda m: np.sum(m["ux"][:, 0] * np.sin(K * yc)) * 2 / L) / K ** 2
-    say(f"shear wave: nu {nu:.5f} (c_s^2 (tau - 1/2) = {0.48 * (TAU - 0.5):.5f})")
+                lambda m: np.sum(m["ux"][:, 0] * np.sin(K * yc)) * 2 / L, storage) / K ** 2
+    say(f"{storage} shear wave: nu {nu:.5f} (c_s^2 (tau - 1/2) = {0.48 * (TAU - 0.5):.5f})")
     assert nu == pytest.approx(0.48 * (TAU - 0.5), rel=2e-3)
     yy, xx = np.mgrid[0:L, 0:L] + 0.5
     nu = _decay(np.ones((L, L)), 1e-3 * np.sin(K * xx) * np.cos(K * yy), -1e-3 * np.cos(K * xx) * np.sin(K * yy),
-                600, 50, lambda m: np.sum(m["ux"] ** 2 + m["uy"] ** 2)) / (4 * K ** 2)
-    say(f"Taylor-Green: nu {nu:.5f}")
+                600, 50, lambda m: np.sum(m["ux"] ** 2 + m["uy"] ** 2), storage) / (4 * K ** 2)
+    say(f"{storage} Taylor-Green: nu {nu:.5f}")
     assert nu == pytest.approx(0.48 * (TAU - 0.5), rel=5e-3)
 
 
-def test_sound_wave():
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_sound_wave(storage):
     xc = np.arange(L) + 0.5
     rr = (1 + 1e-3 * np.cos(K * xc))[None, :] * np.ones((2, 1))
 
@@ -181,8 +183,8 @@ def test_sound_wave():
         ra = np.sum((m["rho_r"][0] - 1) * np.cos(K * xc)) * 2 / L
         ua = np.sum(m["ux"][0] * np.sin(K * xc)) * 2 / L
         return 0.48 * ra ** 2 + ua ** 2
-    gamma = _decay(rr, np.zeros_like(rr), np.zeros_like(rr), 3000, 10, energy) / 2
+    gamma = _decay(rr, np.zeros_like(rr), np.zeros_like(rr), 3000, 10, energy, storage) / 2
     w = 1 / TAU
     want = 0.48 * ((1 / (0.8 * w) - 0.5) + (1 / w - 0.5)) * K ** 2 / 2
-    say(f"sound: Gamma {gamma:.4e} (Chapman-Enskog {want:.4e})")
+    say(f"{storage} sound: Gamma {gamma:.4e} (Chapman-Enskog {want:.4e})")
     assert gamma == pytest.approx(want, rel=5e-3)

@@ -33,6 +33,14 @@ def _cases(storage):
     color = np.where(np.arange(20) < 10, 1, -1).astype(np.int8)
     rr, rb = np.zeros((20, 130)), np.ones((20, 130))
     cases.append((p, serve.init_fields(rr, rb, inlet_color=color), 150, rr, rb, color))
+    # requests with the Navier-Stokes correction (stepped by the other kernel
+    # variant, in a group of their own) and with a contact angle at the walls
+    c = W.bubble_cell(5.0, 2, 24, n=96, collision="mrt", storage=storage)
+    c["params"]["ns_correction"] = True
+    cases.insert(2, (c["params"], serve.init_disk(48, 48, 24, 1.0, 0.0, 0.0, 5.0), 180, c["rho_r"], c["rho_b"],
+                     None))
+    d = W.wall_droplet(120.0, n=64, storage=storage)
+    cases.append((d["params"], serve.init_fields(d["rho_r"], d["rho_b"]), 222, d["rho_r"], d["rho_b"], None))
     return cases
 
 
