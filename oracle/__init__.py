@@ -35,6 +35,7 @@ class OrParams(C.Structure):
         ("slip_lo", C.c_int), ("slip_hi", C.c_int),
         ("contact_angle", C.c_double),
         ("ns_correction", C.c_int),
+        ("gradient", C.c_int),
     ]
 
 
@@ -68,6 +69,7 @@ def lib():
         L.or_omega_eff.restype = C.c_double
         L.or_omega_eff.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
         L.or_gradient3x3.argtypes = [_D, _D]
+        L.or_gradient5x5.argtypes = [_D, _D]
         L.or_perturbation.argtypes = [_D, C.c_double, _D]
         L.or_wetting.argtypes = [_D, _D, C.c_double, _D]
         L.or_recolor.argtypes = [_D, C.c_double, C.c_double, _D, C.c_double, C.c_double,
@@ -142,6 +144,13 @@ def gradient3x3(patch):
     return F
 
 
+def gradient5x5(patch):
+    """Second-neighbour isotropic colour gradient of a 5 x 5 patch [dy][dx]."""
+    F = np.zeros(2)
+    lib().or_gradient5x5(_p(_f64(np.asarray(patch).reshape(25))), _p(F))
+    return F
+
+
 def perturbation(F, A):
     F2 = _f64(F); out = np.zeros(9)
     lib().or_perturbation(_p(F2), A, _p(out))
@@ -207,7 +216,7 @@ class Sim:
                  percolor=False, rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0,
                  tau_b=1.0, delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8,
                  gx=0.0, gy=0.0, u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0,
-                 ns_correction=False, **_ignored):
+                 ns_correction=False, gradient="nearest", **_ignored):
         self.nx, self.ny = nx, ny
         by, slo, shi = self.BC_Y[bc_y]
         p = OrParams(nx=nx, ny=ny,
@@ -217,7 +226,8 @@ class Sim:
                      rho0_r=rho0_r, rho0_b=rho0_b, alpha_light=alpha_light,
                      tau_r=tau_r, tau_b=tau_b, delta=delta, A=A, sigma=sigma, beta=beta,
                      mrt_lambda=mrt_lambda, gx=gx, gy=gy, u_in_r=u_in_r, u_in_b=u_in_b,
-                     p_out=p_out, contact_angle=contact_angle, ns_correction=int(bool(ns_correction)))
+                     p_out=p_out, contact_angle=contact_angle, ns_correction=int(bool(ns_correction)),
+                     gradient={"nearest": 0, "isotropic": 1}[gradient])
         self._params = p
         self._h = lib().or_create(C.byref(p))
         if not self._h:

@@ -50,6 +50,12 @@
  *      rules (R6): parity unpinned (the paper gives no rule; pinned are the
  *      periodic decay rates).  Zou-He H uses the prescribed (inlet) or
  *      measured (outlet) colour fractions of R7.
+ *  R15 the more isotropic gradient the paper mentions (Sec. 4) as an option:
+ *      the 25-point second-neighbour stencil isotropic to 8th order.  Its
+ *      outer ghost cells: beyond an open face the nearest column (R6);
+ *      beyond a wall the inner ghost row (Sec. 2.4 defines solid nodes with
+ *      fluid neighbours only); corner cells beyond both take the inner ghost
+ *      column of the ghost row.  The boundary rule is parity unpinned.
  */
 #include "cg_oracle.h"
 
@@ -239,6 +245,24 @@ void or_gradient3x3(const double *psi9, double *F2)
     }
 }
 
+/* Second-neighbour colour gradient (the more isotropic operator the paper
+ * points to in Sec. 4 as an option, R15): F = sum over the 24 nodes with
+ * |dx|, |dy| <= 2 of w(|c|^2) c psi(x + c), with the weights of the
+ * 8th-order isotropic 25-point stencil, w(1) = 4/21, w(2) = 4/45,
+ * w(4) = 1/60, w(5) = 2/315, w(8) = 1/5040 (second moment sum w c c = I). */
+void or_gradient5x5(const double *psi25, double *F2)
+{
+    F2[0] = F2[1] = 0.0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            int c2 = dx * dx + dy * dy;
+            double w = c2 == 1 ? 4.0 / 21.0 : c2 == 2 ? 4.0 / 45.0 : c2 == 4 ? 1.0 / 60.0
+                     : c2 == 5 ? 2.0 / 315.0 : c2 == 8 ? 1.0 / 5040.0 : 0.0;
+            F2[0] += w * dx * psi25[(dy + 2) * 5 + (dx + 2)];
+            F2[1] += w * dy * psi25[(dy + 2) * 5 + (dx + 2)];
+        }
+}
+
 /* Sec. 2.4: orientation of the colour gradient at a fluid node next to a
  * wall.  n* = F/|F|; the two unit normals that make the angle theta with
  * the wall normal ns; the one closer to n* (ns itself on a tie); |F| kept.
@@ -380,8 +404,8 @@ struct or_sim {
     double *strm;   /* [2][9][ny][nx] streamed + boundary-completed     */
     double *rho;    /* [2][ny][nx] colour densities used by the step    */
     double *ux, *uy;
-    double *psi;    /* [ny+2][nx+2] colour field with ghost layer        */
-    double *q;      /* [2 colours][2 components][ny+2][nx+2] Q^k of Sec. 2.1.3 with ghost layer */
+    double *psi;    /* [ny+4][nx+4] colour field with a ghost layer of two cells */
+    double *q;      /* [2 colours][2 components][ny+4][nx+4] Q^k of Sec. 2.1.3, same layout */
     signed char *inlet_color;
     long step;
 };
@@ -389,6 +413,14 @@ struct or_sim {
 #define POP(a, k, i, y, x) ((a)[((((size_t)(k) * 9 + (i)) * ny + (y)) * nx) + (x)])
 
 static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+/* fields with ghost cells: two cells on every side (the second-neighbour
+ * gradient reaches x +- 2, y +- 2) */
+#define GW 2
+static size_t gidx(const or_sim *s, int x, int y)
+{
+    return (size_t)(y + GW) * (size_t)(s->p.nx + 2 * GW) + (size_t)(x + GW);
+}
 
 or_sim *or_create(const or_params *p)
 {
@@ -407,8 +439,8 @@ or_sim *or_create(const or_params *p)
     s->rho = (double *)calloc(2 * n, sizeof(double));
     s->ux = (double *)calloc(n, sizeof(double));
     s->uy = (double *)calloc(n, sizeof(double));
-    s->psi = (double *)calloc((size_t)(p->nx + 2) * (p->ny + 2), sizeof(double));
-    s->q = (double *)calloc(4 * (size_t)(p->nx + 2) * (p->ny + 2), sizeof(double));
+    s->psi = (double *)calloc((size_t)(p->nx + 2 * GW) * (p->ny + 2 * GW), sizeof(double));
+    s->q = (double *)calloc(4 * (size_t)(p->nx + 2 * GW) * (p->ny + 2 * GW), sizeof(double));
     s->inlet_color = (signed char *)malloc((size_t)p->ny);
     memset(s->inlet_color, 1, (size_t)p->ny);
     return s;
@@ -580,15 +612,15 @@ static double color_field(const or_sim *s, double rho_r, double rho_b)
     return (a - b) / (a + b);
 }
 
-/* value of a field f ([ny+2][nx+2] with ghost layer) at (x, y) in
- * [-1, nx] x [-1, ny], ghost rules of R6 */
+/* value of a field f (ghost layout, gidx) at (x, y) in [-1, nx] x [-1, ny],
+ * ghost rules of R6 */
 static double ghost_value(const or_sim *s, const double *f, int x, int y)
 {
     int nx = s->p.nx, ny = s->p.ny;
     if (s->p.bc_x == OR_BCX_PERIODIC) x = wrap(x, nx);
     if (s->p.bc_y == OR_BCY_PERIODIC) y = wrap(y, ny);
     int xin = x >= 0 && x < nx, yin = y >= 0 && y < ny;
-    if (xin && yin) return f[(size_t)(y + 1) * (nx + 2) + (x + 1)];
+    if (xin && yin) return f[gidx(s, x, y)];
     if (!yin) {
         /* wall (solid) node: W-weighted mean over fluid neighbours, Sec. 2.4 */
         double num = 0.0, den = 0.0;
@@ -596,28 +628,40 @@ static double ghost_value(const or_sim *s, const double *f, int x, int y)
             int fx = x + CX[i], fy = y + CY[i];
             if (s->p.bc_x == OR_BCX_PERIODIC) fx = wrap(fx, nx);
             if (fx < 0 || fx >= nx || fy < 0 || fy >= ny) continue;
-            num += Wt(i) * f[(size_t)(fy + 1) * (nx + 2) + (fx + 1)];
+            num += Wt(i) * f[gidx(s, fx, fy)];
             den += Wt(i);
         }
         return num / den;
     }
     /* open-boundary ghost column: nearest in-domain column */
-    int cxn = x < 0 ? 0 : nx - 1;
-    return f[(size_t)(y + 1) * (nx + 2) + (cxn + 1)];
+    return f[gidx(s, x < 0 ? 0 : nx - 1, y)];
 }
 
-/* fill the ghost layer of f: ghost columns first (they only read the
- * domain), then ghost rows */
+/* fill the ghost cells of f: ghost columns first (they only read the
+ * domain), then the ghost rows next to the domain, then the outer ghost
+ * rows: periodic wrap, or beyond a wall a copy of the inner ghost row (R15:
+ * solid nodes with no fluid neighbour are not defined by Sec. 2.4) */
 static void fill_ghosts(const or_sim *s, double *f)
 {
     int nx = s->p.nx, ny = s->p.ny;
-    for (int y = 0; y < ny; ++y) {
-        f[(size_t)(y + 1) * (nx + 2) + 0] = ghost_value(s, f, -1, y);
-        f[(size_t)(y + 1) * (nx + 2) + (nx + 1)] = ghost_value(s, f, nx, y);
+    for (int y = 0; y < ny; ++y)
+        for (int g = 1; g <= GW; ++g) {
+            f[gidx(s, -g, y)] = ghost_value(s, f, -g, y);
+            f[gidx(s, nx - 1 + g, y)] = ghost_value(s, f, nx - 1 + g, y);
+        }
+    for (int x = -GW; x < nx + GW; ++x) {
+        int xe = x < -1 ? -1 : (x > nx ? nx : x);          /* outer ghost columns: as the inner one */
+        f[gidx(s, x, -1)] = ghost_value(s, f, xe, -1);
+        f[gidx(s, x, ny)] = ghost_value(s, f, xe, ny);
     }
-    for (int x = -1; x <= nx; ++x) {
-        f[(size_t)0 * (nx + 2) + (x + 1)] = ghost_value(s, f, x, -1);
-        f[(size_t)(ny + 1) * (nx + 2) + (x + 1)] = ghost_value(s, f, x, ny);
+    for (int x = -GW; x < nx + GW; ++x) {
+        if (s->p.bc_y == OR_BCY_PERIODIC) {
+            f[gidx(s, x, -2)] = f[gidx(s, x, wrap(-2, ny))];
+            f[gidx(s, x, ny + 1)] = f[gidx(s, x, wrap(ny + 1, ny))];
+        } else {
+            f[gidx(s, x, -2)] = f[gidx(s, x, -1)];
+            f[gidx(s, x, ny + 1)] = f[gidx(s, x, ny)];
+        }
     }
 }
 
@@ -627,11 +671,11 @@ static void fill_ghosts(const or_sim *s, double *f)
 static void pass_color_field(or_sim *s)
 {
     int nx = s->p.nx, ny = s->p.ny;
-    size_t n = (size_t)nx * ny, g = (size_t)(nx + 2) * (ny + 2);
+    size_t n = (size_t)nx * ny, g = (size_t)(nx + 2 * GW) * (ny + 2 * GW);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t c = (size_t)y * nx + x;
-            s->psi[(size_t)(y + 1) * (nx + 2) + (x + 1)] = color_field(s, s->rho[c], s->rho[n + c]);
+            s->psi[gidx(s, x, y)] = color_field(s, s->rho[c], s->rho[n + c]);
         }
     fill_ghosts(s, s->psi);
     if (!s->p.ns_correction) return;
@@ -641,8 +685,8 @@ static void pass_color_field(or_sim *s)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 size_t c = (size_t)y * nx + x;
-                qx[(size_t)(y + 1) * (nx + 2) + (x + 1)] = a * s->rho[k * n + c] * s->ux[c];
-                qy[(size_t)(y + 1) * (nx + 2) + (x + 1)] = a * s->rho[k * n + c] * s->uy[c];
+                qx[gidx(s, x, y)] = a * s->rho[k * n + c] * s->ux[c];
+                qy[gidx(s, x, y)] = a * s->rho[k * n + c] * s->uy[c];
             }
         fill_ghosts(s, qx);
         fill_ghosts(s, qy);
@@ -653,12 +697,11 @@ static void pass_color_field(or_sim *s)
  * eq. (colorGradient) (Sec. 2.1.3) */
 static void q_divergence(const or_sim *s, int k, int x, int y, double *dqx, double *dqy)
 {
-    int nx = s->p.nx, ny = s->p.ny;
-    size_t g = (size_t)(nx + 2) * (ny + 2);
+    size_t g = (size_t)(s->p.nx + 2 * GW) * (s->p.ny + 2 * GW);
     double px[9], py[9], Gx[2], Gy[2];
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
-            size_t o = (size_t)(y + 1 + dy) * (nx + 2) + (x + 1 + dx);
+            size_t o = gidx(s, x + dx, y + dy);
             px[(dy + 1) * 3 + (dx + 1)] = s->q[(2 * k) * g + o];
             py[(dy + 1) * 3 + (dx + 1)] = s->q[(2 * k + 1) * g + o];
         }
@@ -681,12 +724,20 @@ static void pass_collide(or_sim *s)
             size_t c = (size_t)y * nx + x;
             double rk[2] = {s->rho[c], s->rho[n + c]};
             double u = s->ux[c], v = s->uy[c];
-            /* colour gradient from the extended psi field */
-            double patch[9], F[2];
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx)
-                    patch[(dy + 1) * 3 + (dx + 1)] = s->psi[(size_t)(y + 1 + dy) * (nx + 2) + (x + 1 + dx)];
-            or_gradient3x3(patch, F);
+            /* colour gradient from the extended psi field: eq. (colorGradient),
+               or the second-neighbour isotropic stencil (R15) */
+            double patch[25], F[2];
+            for (int dy = -2; dy <= 2; ++dy)
+                for (int dx = -2; dx <= 2; ++dx)
+                    patch[(dy + 2) * 5 + (dx + 2)] = s->psi[gidx(s, x + dx, y + dy)];
+            if (p->gradient == 1) {
+                or_gradient5x5(patch, F);
+            } else {
+                double p9[9];
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) p9[(dy + 1) * 3 + (dx + 1)] = patch[(dy + 2) * 5 + (dx + 2)];
+                or_gradient3x3(p9, F);
+            }
             if (p->bc_y == OR_BCY_WALLS && p->contact_angle >= 0.0 && (y == 0 || y == ny - 1)) {
                 /* wetting (Sec. 2.4, R11): the wall normal points into the fluid and
                    the gradient points into red, so the angle between them is the
@@ -696,7 +747,7 @@ static void pass_collide(or_sim *s)
                 F[0] = Fw[0];
                 F[1] = Fw[1];
             }
-            double psi = patch[4];
+            double psi = patch[12];
             double w = or_omega_eff(psi, s->omega[0], s->omega[1], p->delta);
             double A = p->sigma > 0.0 ? 9.0 * p->sigma * w / 4.0 : p->A;
 

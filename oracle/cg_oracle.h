@@ -50,6 +50,8 @@ typedef struct {
                                in degrees (Sec. 2.4); < 0: no adjustment of the colour gradient */
     int ns_correction;      /* 1: Sec. 2.1.3 Navier-Stokes correction (Hermite equilibrium everywhere,
                                the MRT source U^k, Hermite terms of the Zou-He completion) */
+    int gradient;           /* 0: eq. (colorGradient), nearest neighbours; 1: the second-neighbour
+                               8th-order isotropic stencil (R15) */
 } or_params;
 
 typedef struct or_sim or_sim;
@@ -61,6 +63,7 @@ void   or_alphas(double rho0_r, double rho0_b, double alpha_light, double *alpha
 void   or_equilibrium(double rho_k, double ux, double uy, double alpha_k, double *out9);
 double or_omega_eff(double psi, double omega_r, double omega_b, double delta);
 void   or_gradient3x3(const double *psi9, double *F2);   /* psi9[(dy+1)*3+(dx+1)] */
+void   or_gradient5x5(const double *psi25, double *F2);  /* psi25[(dy+2)*5+(dx+2)] */
 void   or_equilibrium_hermite(double rho_k, double ux, double uy, double alpha_k, double *out9);
 /* Sec. 2.1.3: U = M^{-1} C from dQx/dx, dQy/dy and the rates s_1, s_7 */
 void   or_ns_source(double dQxdx, double dQydy, double s1, double s7, double *out9);

@@ -33,7 +33,8 @@ import numpy as np
 DEFAULTS = dict(bc_x="periodic", bc_y="periodic", collision="bgk", storage="f32",
                 rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0, tau_b=1.0,
                 delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8, gx=0.0, gy=0.0,
-                u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0, ns_correction=False)
+                u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0, ns_correction=False,
+                gradient="nearest")
 
 
 def params(**kw):

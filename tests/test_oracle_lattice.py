@@ -450,3 +450,46 @@ def test_sound_wave_damping(orc):
     w = 1 / NSC_TAU
     gamma = 0.48 * ((1 / (0.8 * w) - 0.5) + (1 / w - 0.5)) * k ** 2 / 2
     assert _rate(t, e) / 2 == pytest.approx(gamma, rel=5e-3)
+
+
+# --------------------------------------------- second-neighbour gradient (R15)
+def test_isotropic_gradient_lowers_spurious_currents(orc):
+    """The paper's remark on a more isotropic gradient: the static bubble's
+    spurious currents after 5000 steps drop to under 60% of those of the
+    nearest-neighbour stencil (measured: 2.4e-6 against 4.7e-6)."""
+    c = W.static_bubble(n=64, radius=16)
+    u = {}
+    for grad in ("nearest", "isotropic"):
+        s = orc.Sim(**dict(c["params"], gradient=grad)).init(c["rho_r"], c["rho_b"])
+        s.step(5000)
+        m = s.moments()
+        u[grad] = np.hypot(m["ux"], m["uy"]).max()
+    assert u["isotropic"] < 0.6 * u["nearest"]
+
+
+@pytest.mark.parametrize("bc", ["walls", "freeslip", "open"])
+def test_isotropic_gradient_at_boundaries(orc, bc):
+    """Second ghost rows and columns (R15): a mirror-symmetric droplet on a
+    wall stays mirror-symmetric, colour masses are conserved; with an open
+    channel the run stays finite."""
+    if bc == "open":
+        p = W.params(nx=64, ny=20, bc_x="open", bc_y="walls", rho0_r=2.0, rho0_b=1.0, tau_r=0.8, tau_b=0.9,
+                     A=1e-3, u_in_r=0.01, u_in_b=0.01, p_out=0.48, gradient="isotropic")
+        color = np.where(np.arange(20) < 8, 1, -1).astype(np.int8)
+        rr = np.where(color[:, None] > 0, 2.0, 0.0) * np.ones((1, 64))
+        s = orc.Sim(**p).init(rr, np.where(color[:, None] > 0, 0.0, 1.0) * np.ones((1, 64)))
+        s.set_inlet_color(color)
+        s.step(300)
+        m = s.moments()
+        assert all(np.all(np.isfinite(m[k])) for k in ("rho_r", "rho_b", "ux", "uy"))
+        return
+    c = W.wall_droplet(70.0, n=40, bc_y=bc)
+    p = dict(c["params"], gradient="isotropic")
+    s = orc.Sim(**p).init(c["rho_r"], c["rho_b"])
+    m0 = s.moments()
+    s.step(400)
+    m = s.moments()
+    psi = (m["rho_r"] - m["rho_b"]) / (m["rho_r"] + m["rho_b"])
+    assert np.max(np.abs(psi - psi[:, ::-1])) < 1e-12
+    for k in ("rho_r", "rho_b"):
+        assert m[k].sum() == pytest.approx(m0[k].sum(), rel=1e-12)

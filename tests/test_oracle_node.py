@@ -324,3 +324,38 @@ def test_zouhe_hermite_exact_on_equilibrium(orc, alphas):
         if abs(kap * ux) > 1e-4:
             _, N0 = orc.zouhe_west(np.where(np.isin(np.arange(9), [1, 5, 8]), 0.0, E), ux, uy, 0.0)
             assert not np.allclose(N0, E, atol=1e-8)
+
+
+# --------------------------------------------- second-neighbour gradient (R15)
+def _poly_patch(f, x0, y0, r):
+    return np.array([[f(x0 + dx, y0 + dy) for dx in range(-r, r + 1)] for dy in range(-r, r + 1)])
+
+
+@pytest.mark.parametrize("deg", [1, 3, 5, 7])
+def test_isotropic_gradient_exact_on_harmonic_polynomials(orc, deg):
+    """The 25-point stencil's error on a polynomial is a sum of isotropic
+    tensors (moments isotropic up to 8th order) times derivatives of its
+    Laplacian, so it differentiates harmonic polynomials up to degree 7
+    exactly; the nearest-neighbour stencil of eq. (colorGradient) (isotropic
+    to 4th order) stops at degree 3."""
+    f = lambda x, y: ((x + 1j * y) ** deg).real
+    x0, y0 = 0.3, -0.7
+    g = deg * (x0 + 1j * y0) ** (deg - 1)
+    exact = np.array([g.real, -g.imag])
+    F5 = orc.gradient5x5(_poly_patch(f, x0, y0, 2))
+    assert np.allclose(F5, exact, rtol=0, atol=1e-13 * max(1.0, np.abs(exact).max()))
+    F3 = orc.gradient3x3(_poly_patch(f, x0, y0, 1))
+    if deg <= 3:
+        assert np.allclose(F3, exact, atol=1e-13)
+    else:
+        assert np.abs(F3 - exact).max() > 0.1
+
+
+def test_isotropic_gradient_of_quadratics(orc):
+    """Second moment sum w c c = I: exact gradient of any quadratic."""
+    for _ in range(5):
+        a = RNG.normal(size=6)
+        f = lambda x, y: a[0] + a[1] * x + a[2] * y + a[3] * x * x + a[4] * x * y + a[5] * y * y
+        x0, y0 = RNG.uniform(-1, 1, 2)
+        exact = [a[1] + 2 * a[3] * x0 + a[4] * y0, a[2] + a[4] * x0 + 2 * a[5] * y0]
+        assert np.allclose(orc.gradient5x5(_poly_patch(f, x0, y0, 2)), exact, atol=1e-13)
