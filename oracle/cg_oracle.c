@@ -650,7 +650,9 @@ static void fill_ghosts(const or_sim *s, double *f)
             f[gidx(s, nx - 1 + g, y)] = ghost_value(s, f, nx - 1 + g, y);
         }
     for (int x = -GW; x < nx + GW; ++x) {
-        int xe = x < -1 ? -1 : (x > nx ? nx : x);          /* outer ghost columns: as the inner one */
+        /* periodic x: the ghost row wraps; beyond an open face the outer
+           ghost columns repeat the inner one */
+        int xe = s->p.bc_x == OR_BCX_PERIODIC ? x : (x < -1 ? -1 : (x > nx ? nx : x));
         f[gidx(s, x, -1)] = ghost_value(s, f, xe, -1);
         f[gidx(s, x, ny)] = ghost_value(s, f, xe, ny);
     }

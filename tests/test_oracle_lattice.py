@@ -493,3 +493,17 @@ def test_isotropic_gradient_at_boundaries(orc, bc):
     assert np.max(np.abs(psi - psi[:, ::-1])) < 1e-12
     for k in ("rho_r", "rho_b"):
         assert m[k].sum() == pytest.approx(m0[k].sum(), rel=1e-12)
+
+
+def test_isotropic_gradient_ghost_rows_wrap_in_x(orc):
+    """With walls and periodic x the ghost rows are periodic too: shifting
+    the whole field by a column commutes with the step (a ghost row built
+    from the wrong columns breaks it at the wall rows)."""
+    rr, rb, ux, uy = W.random_fields(24, 10, seed=4, rho0_r=1.0, rho0_b=3.0, umax=0.01)
+    p = W.params(nx=24, ny=10, bc_y="walls", rho0_r=1.0, rho0_b=3.0, tau_r=0.8, tau_b=0.9, A=1e-3,
+                 gradient="isotropic")
+    a = orc.Sim(**p).init(rr, rb, ux, uy)
+    b = orc.Sim(**p).init(*(np.roll(f, 5, axis=1) for f in (rr, rb, ux, uy)))
+    a.step(20)
+    b.step(20)
+    assert np.max(np.abs(np.roll(a.get_pops(), 5, axis=3) - b.get_pops())) < 1e-13
