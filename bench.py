@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
     ap.add_argument("--ns-correction", action="store_true",
                     help="Navier-Stokes correction of Sec. 2.1.3 (needs --collision mrt)")
+    ap.add_argument("--gradient", default="nearest", choices=["nearest", "isotropic"],
+                    help="colour-gradient stencil: nearest neighbours, or the second-neighbour isotropic one")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--strip", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
@@ -426,6 +428,8 @@ def main():
             raise SystemExit("--ns-correction needs --collision mrt")
         for c in cells:
             c["params"]["ns_correction"] = True
+    for c in cells:
+        c["params"]["gradient"] = args.gradient
     lats = []
     for c in cells:
         lat = capi.Lattice(c["params"], stream=sid)
@@ -463,7 +467,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            key = f"{args.workload}/{args.storage}/{args.collision}" + ("/nsc" if args.ns_correction else "")
+            key = (f"{args.workload}/{args.storage}/{args.collision}" + ("/nsc" if args.ns_correction else "")
+                   + ("/iso" if args.gradient == "isotropic" else ""))
             if tr.get("kernel_hash") == kernel_hash() and key in tr.get("per_launch", {}):
                 traffic = tr["per_launch"][key]
         except (OSError, ValueError):
@@ -501,7 +506,7 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": wname, "lattices": len(cells), "nx": p0["nx"], "ny": p0["ny"],
                    "nodes": nodes, "storage": args.storage, "collision": args.collision,
-                   "ns_correction": bool(args.ns_correction),
+                   "ns_correction": bool(args.ns_correction), "gradient": args.gradient,
                    "steps_simulated": args.warmup + args.steps, "seed": args.seed,
                    "launch": f"batched k_step, {launches} launch(es) per step (lattices grouped to fit the "
                              "Infinity Cache, groups in turns of 256 steps), HIP-graph replay of 32 steps"},

@@ -107,6 +107,16 @@ typedef struct {
      * c_s,k^2 (tau_k - 1/2) instead of (tau_k - 1/2) / 3. */
     int32_t ns_correction;   /* 0 or 1                                                   */
     int32_t reserved1;       /* must be 0                                                */
+    /* Colour gradient: 0 = eq. (colorGradient), nearest neighbours; 1 = the
+     * more isotropic operator the paper points to (Sec. 4): second
+     * neighbours, 25 points, F = sum w(|c|^2) c psi(x + c) with w = 4/21,
+     * 4/45, 1/60, 2/315, 1/5040 for |c|^2 = 1, 2, 4, 5, 8 (isotropic to 8th
+     * order).  Beyond an open face the colour field takes the nearest column;
+     * two rows beyond a wall it repeats the ghost row of Sec. 2.4; corner
+     * cells beyond both repeat the inner ghost column.  Lower spurious
+     * currents, more work per node. */
+    int32_t gradient;        /* 0 or 1                                                   */
+    int32_t reserved2;       /* must be 0                                                */
 } lbm_params;
 
 typedef struct {

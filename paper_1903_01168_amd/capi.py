@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcglbm.so")
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_BUSY, LBM_E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6
+GRADIENT = {"nearest": 0, "isotropic": 1}
 BC = {"periodic": 0, "bounceback": 1, "zouhe_velocity": 2, "zouhe_pressure": 3, "freeslip": 4}
 # y-face pairs (low, high) by the ``bc_y`` names of ``workloads.params``
 BC_Y = {"periodic": ("periodic", "periodic"), "walls": ("bounceback", "bounceback"),
@@ -42,6 +43,7 @@ class LbmParams(C.Structure):
         ("u_in_r", C.c_double), ("u_in_b", C.c_double), ("p_out", C.c_double),
         ("wetting", C.c_int32), ("reserved0", C.c_int32), ("contact_angle", C.c_double),
         ("ns_correction", C.c_int32), ("reserved1", C.c_int32),
+        ("gradient", C.c_int32), ("reserved2", C.c_int32),
     ]
 
 
@@ -129,7 +131,8 @@ def make_params(p: dict) -> LbmParams:
         beta=p["beta"], mrt_lambda=p["mrt_lambda"], gx=p["gx"], gy=p["gy"],
         u_in_r=p["u_in_r"], u_in_b=p["u_in_b"], p_out=p["p_out"],
         wetting=1 if ca >= 0 else 0, contact_angle=ca if ca >= 0 else 0.0,
-        ns_correction=int(bool(p.get("ns_correction", False))))
+        ns_correction=int(bool(p.get("ns_correction", False))),
+        gradient=GRADIENT[p.get("gradient", "nearest")])
 
 
 def _f64(a, shape):

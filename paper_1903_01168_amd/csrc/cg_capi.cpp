@@ -106,6 +106,9 @@ int validate(const lbm_params *p, std::string &msg)
     if ((p->ns_correction != 0 && p->ns_correction != 1) || p->reserved1 != 0) {
         msg = "ns_correction must be 0 or 1 and reserved1 0"; return LBM_E_INVAL;
     }
+    if ((p->gradient != 0 && p->gradient != 1) || p->reserved2 != 0) {
+        msg = "gradient must be 0 or 1 and reserved2 0"; return LBM_E_INVAL;
+    }
     if (p->ns_correction && p->collision != LBM_COLL_MRT) {
         msg = "the Navier-Stokes correction needs MRT collision"; return LBM_E_INVAL;
     }
@@ -186,6 +189,7 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
     if (p->gx != 0.0 || p->gy != 0.0) f |= cgd::F_FORCE;
     if (p->wetting) f |= cgd::F_WET;
     if (p->ns_correction) f |= cgd::F_NSC;
+    if (p->gradient == 1) f |= cgd::F_ISO;
     for (int k = 0; k < 2; ++k) d.k3[k] = (float)(0.8 - 1.8 * alpha[k]);   // 3 c_s,k^2 - 1
     d.flags = f;
     // wetting (Sec. 2.4): the gradient makes the angle 180 - contact_angle
@@ -202,10 +206,11 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
 // which pays from about 4M nodes (8192 x 512 channel: +3% in FP32).
 int default_tx(int nx, int ny) { return (long long)nx * ny >= (1LL << 22) ? 256 : 64; }
 
-// A wavefront writes 60 columns (it reads 2 more on each side).
-static const int kWaveCols = 60;
-
-static int wave_tiles(int nx) { return (nx + kWaveCols - 1) / kWaveCols; }
+static int wave_tiles(int nx, bool iso)
+{
+    const int cols = cgd::wave_cols(iso);
+    return (nx + cols - 1) / cols;
+}
 
 int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req)
 {
@@ -276,7 +281,7 @@ void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int
     d.plane = L.plane;
     d.strip = strip;
     const int waves = tx / 64;
-    d.tiles_x = (wave_tiles(p->nx) + waves - 1) / waves;   // workgroups across x
+    d.tiles_x = (wave_tiles(p->nx, p->gradient == 1) + waves - 1) / waves;   // workgroups across x
     d.tiles_y = (p->ny + strip - 1) / strip;
 }
 
@@ -498,7 +503,7 @@ static int build_graph(lbm_ctx *c, int parity)
     hipError_t le = hipSuccess;
     for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
         le = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (parity + j) & 1, 0, c->cap_stream,
-                              c->p.ns_correction != 0);
+                              cgd::step_variant(c->desc));
     e = hipStreamEndCapture(c->cap_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -531,7 +536,7 @@ int lbm_step(lbm_ctx *c, int64_t n)
     }
     for (; n > 0; --n) {
         hipError_t e = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (int)(c->steps & 1), 0, c->stream,
-                                        c->p.ns_correction != 0);
+                                        cgd::step_variant(c->desc));
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->steps++;
     }
@@ -711,7 +716,7 @@ struct BatchGroup {
     std::vector<SlotDesc> slots;
     SlotDesc *d_slots = nullptr;
     int tiles = 0;
-    bool nsc = false;                   // some lattice carries the Navier-Stokes correction
+    int variant = 0;                    // step-kernel variant of its lattices (one per group)
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
@@ -779,7 +784,7 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
     std::vector<char> kind;
     for (int i = 0; i < n; ++i) {
         bytes.push_back(2 * ctxs[i]->buf_bytes);
-        kind.push_back(ctxs[i]->p.ns_correction != 0);
+        kind.push_back((char)cgd::step_variant(ctxs[i]->desc));
     }
     const std::vector<int> first = cache_groups(bytes, kind);
     b->groups.resize(first.size() - 1);
@@ -797,7 +802,7 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
             if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer
             tiles += (long long)d.tiles_x * d.tiles_y;
             G.slots.push_back(d);
-            if (d.flags & cgd::F_NSC) G.nsc = true;
+            G.variant = cgd::step_variant(d);
         }
         if (tiles > INT_MAX / 2) {
             lbm_batch_destroy(b);
@@ -843,7 +848,7 @@ static int batch_graph(lbm_batch *b, BatchGroup &G, int parity)
     hipError_t le = hipSuccess;
     for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
         le = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (parity + j) & 1, 0,
-                              b->cap_stream, G.nsc);
+                              b->cap_stream, G.variant);
     e = hipStreamEndCapture(b->cap_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -876,7 +881,7 @@ static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n)
     }
     for (; n > 0; --n, ++t) {
         hipError_t e = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (int)(t & 1), 0,
-                                        b->stream, G.nsc);
+                                        b->stream, G.variant);
         if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     }
     return LBM_OK;

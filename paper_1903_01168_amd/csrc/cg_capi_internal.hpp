@@ -65,9 +65,9 @@ constexpr size_t kCacheBudget = 192ull << 20;
 // the device bytes that each lattice's steps touch (its two buffers).
 std::vector<int> cache_groups(const std::vector<size_t> &bytes);
 // The same within each run of consecutive lattices of one kind (kind[i]: the
-// lattice needs the Navier-Stokes variant of the step kernel), so that every
-// lattice is stepped by the kernel variant it would get alone and its result
-// does not depend on its neighbours.
+// step-kernel variant the lattice needs), so that every lattice is stepped by
+// the kernel variant it would get alone and its result does not depend on
+// its neighbours.
 std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind);
 void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip);
 

@@ -41,8 +41,16 @@ static_assert(cx(mirror_y(5)) == cx(5) && cy(mirror_y(5)) == -cy(5) && cx(mirror
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
 
 enum : int { F_XPER = 1, F_XOPEN = 2, F_YPER = 4, F_MRT = 8, F_SIGMA = 16, F_FORCE = 32, F_SLIP_LO = 64,
-             F_SLIP_HI = 128, F_WET = 256, F_NSC = 512 };
+             F_SLIP_HI = 128, F_WET = 256, F_NSC = 512, F_ISO = 1024 };
 enum : int { ST_F32 = 0, ST_F16S = 1, ST_BF16S = 2 };
+
+// A wavefront's 64 lanes hold consecutive columns: it writes the middle 60
+// and reads 2 more on each side for the nearest-neighbour gradient; the
+// second-neighbour gradient reaches 2 columns out and builds ghost rows
+// from 1 column beyond that, so there the wavefront writes 58 and reads 3
+// more on each side.
+__host__ __device__ constexpr int wave_halo(bool iso) { return iso ? 3 : 2; }
+__host__ __device__ constexpr int wave_cols(bool iso) { return 64 - 2 * wave_halo(iso); }
 
 // ------------------------------------------------------------- descriptor --
 // One lattice ("slot") of a launch.  Built on the host; read with scalar loads.

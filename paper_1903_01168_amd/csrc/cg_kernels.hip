@@ -3,7 +3,8 @@
 //  k_step      one fused time step over a set of lattices ("slots"): pull
 //              gather + boundary completion, colour field, S2I4 gradient,
 //              omega_eff, BGK/MRT, perturbation, recolouring, store.  Every
-//              wavefront owns 60 columns (plus 2 overlap columns on each side)
+//              wavefront owns 60 columns (plus 2 overlap columns on each side;
+//              58 and 3 with the second-neighbour gradient)
 //              of a strip of rows and marches up the strip on its own.
 //  k_init      equilibrium initialisation from FP32 fields.
 //  k_moments   fields at the current step (+ FP64 per-block diagnostics).
@@ -53,15 +54,15 @@ struct Psi3 {
 
 __device__ __forceinline__ Psi3 psi3(float c) { return Psi3{from_west(c), c, from_east(c)}; }
 
-// Wave tile: 64 lanes cover columns xw-2 .. xw+61 and write xw .. xw+59.
-constexpr int kOut = 60;
+// Wave tile: 64 lanes cover columns xw-h .. xw+63-h and write the middle
+// 64-2h (h = wave_halo: 2, or 3 with the second-neighbour gradient).
 
 // One fused time step.  Every wavefront owns kOut columns of a strip of rows
 // and marches up the strip on its own (no LDS, no barrier): the colour field
 // of the rows y-1, y, y+1 lives in registers, horizontal neighbours come from
 // the adjacent lanes, and the populations of row y+2 are requested before row
 // y collides.
-template <int ST, int W, bool NSC>
+template <int ST, int W, bool NSC, bool ISO>
 __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
                                                  int parity, int launch_idx)
 {
@@ -77,6 +78,7 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
     const int txi = lt - tyi * S.tiles_x;
     const int nx = S.nx, ny = S.ny;
     const int lane = threadIdx.x & 63;
+    constexpr int kHalo = wave_halo(ISO), kOut = wave_cols(ISO);
     const int xw = (txi * W + (int)(threadIdx.x >> 6)) * kOut;
     if (xw >= nx) return;                      // uniform per wavefront
     const int y0 = tyi * S.strip;
@@ -84,9 +86,9 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
     const bool yper = S.flags & F_YPER;
     const bool xper = S.flags & F_XPER;
 
-    const int xl = xw - 2 + lane;              // the lane's column (may lie outside the lattice)
+    const int xl = xw - kHalo + lane;          // the lane's column (may lie outside the lattice)
     const int xg = xper ? wrapi(xl, nx) : (xl < 0 ? 0 : (xl >= nx ? nx - 1 : xl));
-    const bool out_lane = lane >= 2 && lane < 62 && xl < nx;
+    const bool out_lane = lane >= kHalo && lane < 64 - kHalo && xl < nx;
     const XCols xc = make_cols<ST>(S, xg);
     const Halves src = halves<ST>(S, parity ? S.buf[1] : S.buf[0]);
     const Halves dst = halves<ST>(S, parity ? S.buf[0] : S.buf[1]);
@@ -147,6 +149,136 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
     const int d = (tyi & 1) ? -1 : 1;
     const int ys = d > 0 ? y0 : y1 - 1;       // first row written
     const int ye = d > 0 ? y1 : y0 - 1;       // one past the last row written
+
+    if constexpr (ISO) {
+        // Second-neighbour colour gradient: 25 points, isotropic to 8th
+        // order (weights w(|c|^2): 4/21, 4/45, 1/60, 2/315, 1/5040 for
+        // |c|^2 = 1, 2, 4, 5, 8).  The colour field of rows y-2d .. y+2d
+        // lives in registers, per row its value and the lane values one and
+        // two columns east and west; the populations of row y+3d are
+        // requested before row y collides, rows y+d and y+2d are complete.
+        struct Psi5 {
+            float c, e1, w1, e2, w2;
+        };
+        auto psi5 = [&](float c) -> Psi5 {
+            const float e1 = from_east(c), w1 = from_west(c);
+            return Psi5{c, e1, w1, from_east(e1), from_west(w1)};
+        };
+        // ghost row next to a wall from the adjacent real row (the rule of
+        // ghost()); lanes two columns beyond an open face, which no fluid
+        // node neighbours, take the inner ghost column's value
+        auto ghost5 = [&](const Psi5 &f) -> Psi5 {
+            const float g = ((in0 ? 4.f * f.c : 0.f) + (inw ? f.w1 : 0.f) + (ine ? f.e1 : 0.f)) * ginv;
+            const float ge = from_east(g), gw = from_west(g);
+            return psi5(gden > 0.f ? g : (xl < 0 ? ge : gw));
+        };
+        // Rows at the same distance ahead and behind enter as sums (x) or
+        // differences (y) before any weight multiplies them, so that the
+        // result does not depend on the marching direction (bit for bit,
+        // whatever the strip height)
+        auto dx1 = [](const Psi5 &p) { return p.e1 - p.w1; };
+        auto dx2 = [](const Psi5 &p) { return p.e2 - p.w2; };
+        auto sx1 = [](const Psi5 &p) { return p.e1 + p.w1; };
+        auto sx2 = [](const Psi5 &p) { return p.e2 + p.w2; };
+        auto wanted = [&](int r) { return (d > 0 ? r <= y1 + 1 : r >= y0 - 2) && gathered(r); };
+
+        Psi5 pb2, pb1, p0, pa1;                // rows y-2d, y-d, y, y+d
+        QRow qb{}, q0{}, qa{};                 // Q partial sums of rows y-d, y, y+d (NSC)
+        Node cur, nxt;                         // rows y and y+d
+        {
+            const bool hb2 = gathered(ys - 2 * d), hb1 = gathered(ys - d), ha1 = gathered(ys + d);
+            Raw18<ST> rb2, rb1, ra1;
+            const RowSrc wb2 = make_row<ST>(S, hb2 ? real_row(ys - 2 * d) : ys);
+            const RowSrc wb1 = make_row<ST>(S, hb1 ? real_row(ys - d) : ys);
+            const RowSrc w0 = make_row<ST>(S, ys);
+            const RowSrc wa1 = make_row<ST>(S, ha1 ? real_row(ys + d) : ys);
+            if (hb2) rb2 = issue<ST>(S, src, xc, wb2);
+            if (hb1) rb1 = issue<ST>(S, src, xc, wb1);
+            const Raw18<ST> r0 = issue<ST>(S, src, xc, w0);
+            if (ha1) ra1 = issue<ST>(S, src, xc, wa1);
+            cur = finish<ST>(S, r0, xc, w0);
+            p0 = psi5(color_field(S, cur.rr, cur.rb));
+            if (nsc) q0 = qreal(cur);
+            if (hb1) {
+                const Node t = finish<ST>(S, rb1, xc, wb1);
+                pb1 = psi5(color_field(S, t.rr, t.rb));
+                if (nsc) qb = qreal(t);
+            } else {
+                pb1 = ghost5(p0);
+                if (nsc) qb = qghost(cur);
+            }
+            if (hb2) {
+                const Node t = finish<ST>(S, rb2, xc, wb2);
+                pb2 = psi5(color_field(S, t.rr, t.rb));
+            } else {
+                pb2 = hb1 ? ghost5(pb1) : pb1;   // beyond a wall: distance 1, or the inner ghost row
+            }
+            if (ha1) {
+                nxt = finish<ST>(S, ra1, xc, wa1);
+                pa1 = psi5(color_field(S, nxt.rr, nxt.rb));
+                if (nsc) qa = qreal(nxt);
+            } else {
+                pa1 = ghost5(p0);
+                if (nsc) qa = qghost(cur);
+            }
+        }
+        bool hp = wanted(ys + 2 * d);
+        Raw18<ST> pend;
+        if (hp) pend = issue<ST>(S, src, xc, make_row<ST>(S, real_row(ys + 2 * d)));
+
+        const uint32_t rowbytes = (uint32_t)S.pitch * Codec<ST>::bytes;
+        const float fd = (float)d;
+        for (int y = ys; y != ye; y += d) {
+            Node nn;                           // row y+2d
+            Psi5 pa2;
+            QRow q2{};
+            if (hp) {
+                nn = finish<ST>(S, pend, xc, make_row<ST>(S, real_row(y + 2 * d)));
+                pa2 = psi5(color_field(S, nn.rr, nn.rb));
+                if (nsc) q2 = qreal(nn);
+            } else if (gathered(y + d)) {       // row y+2d is the ghost row next to a wall
+                pa2 = ghost5(pa1);
+                if (nsc) q2 = qghost(nxt);
+            } else {                           // two rows beyond a wall: the inner ghost row
+                pa2 = pa1;
+            }
+            hp = wanted(y + 3 * d);
+            if (hp) pend = issue<ST>(S, src, xc, make_row<ST>(S, real_row(y + 3 * d)));
+            if (out_lane) {
+                // F_x = sum over rows dy of w(1+dy^2) (psi(+1) - psi(-1)) + 2 w(4+dy^2) (psi(+2) - psi(-2));
+                // F_y = sum over rows of dy [w(dy^2) psi(0) + w(1+dy^2) (psi(+1) + psi(-1))
+                //                            + w(4+dy^2) (psi(+2) + psi(-2))]
+                float Fx = (4.f / 21.f) * dx1(p0) + (2.f / 60.f) * dx2(p0) + (4.f / 45.f) * (dx1(pa1) + dx1(pb1)) +
+                           (4.f / 315.f) * (dx2(pa1) + dx2(pb1)) + (2.f / 315.f) * (dx1(pa2) + dx1(pb2)) +
+                           (2.f / 5040.f) * (dx2(pa2) + dx2(pb2));
+                float Fy = fd * ((4.f / 21.f) * (pa1.c - pb1.c) + (4.f / 45.f) * (sx1(pa1) - sx1(pb1)) +
+                                 (2.f / 315.f) * (sx2(pa1) - sx2(pb1)) +
+                                 2.f * ((1.f / 60.f) * (pa2.c - pb2.c) + (2.f / 315.f) * (sx1(pa2) - sx1(pb2)) +
+                                        (1.f / 5040.f) * (sx2(pa2) - sx2(pb2))));
+                if ((S.flags & F_WET) && (y == 0 || y == ny - 1)) wet(S, y == 0, Fx, Fy);
+                float outr[9], outb[9];
+                if constexpr (NSC) {
+                    const float dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
+                    const float dqy = fd * (qa.s - qb.s);
+                    collide<true>(S, cur, p0.c, Fx, Fy, outr, outb, nsc, dqx, dqy);
+                } else {
+                    collide(S, cur, p0.c, Fx, Fy, outr, outb);
+                }
+                if (ST == ST_F32) conserve(cur, outr, outb);
+                store18<ST>(S, dst, xc.o0, (uint32_t)y * rowbytes, outr, outb, cur.mr, cur.mb);
+            }
+            pb2 = pb1;
+            pb1 = p0;
+            p0 = pa1;
+            pa1 = pa2;
+            qb = q0;
+            q0 = qa;
+            qa = q2;
+            cur = nxt;
+            nxt = nn;
+        }
+        return;
+    }
 
     // prologue: the row behind the first one, and the first one
     Psi3 pb, p0;                               // colour field of rows y-d and y
@@ -410,28 +542,38 @@ __global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uin
 }
 
 // ------------------------------------------------------------- launchers --
-template <int ST, bool NSC>
-static hipError_t step_st(int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx, hipStream_t s)
+template <int ST, bool NSC, bool ISO>
+static hipError_t step_v(int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx, hipStream_t s)
 {
     switch (tx) {
-    case 64: hipLaunchKernelGGL((k_step<ST, 1, NSC>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
-    case 128: hipLaunchKernelGGL((k_step<ST, 2, NSC>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
-    case 256: hipLaunchKernelGGL((k_step<ST, 4, NSC>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
+    case 64: hipLaunchKernelGGL((k_step<ST, 1, NSC, ISO>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
+    case 128: hipLaunchKernelGGL((k_step<ST, 2, NSC, ISO>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
+    case 256: hipLaunchKernelGGL((k_step<ST, 4, NSC, ISO>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int ST>
+static hipError_t step_st(int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx, hipStream_t s,
+                          int variant)
+{
+    switch (variant) {
+    case 0: return step_v<ST, false, false>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_NSC: return step_v<ST, true, false>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_ISO: return step_v<ST, false, true>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_NSC | KV_ISO: return step_v<ST, true, true>(tx, d, nslots, tiles, parity, idx, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_step(int storage, int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx,
-                       hipStream_t s, bool nsc)
+                       hipStream_t s, int variant)
 {
     switch (storage) {
-    case ST_F32: return nsc ? step_st<ST_F32, true>(tx, d, nslots, tiles, parity, idx, s)
-                            : step_st<ST_F32, false>(tx, d, nslots, tiles, parity, idx, s);
-    case ST_F16S: return nsc ? step_st<ST_F16S, true>(tx, d, nslots, tiles, parity, idx, s)
-                             : step_st<ST_F16S, false>(tx, d, nslots, tiles, parity, idx, s);
-    case ST_BF16S: return nsc ? step_st<ST_BF16S, true>(tx, d, nslots, tiles, parity, idx, s)
-                              : step_st<ST_BF16S, false>(tx, d, nslots, tiles, parity, idx, s);
+    case ST_F32: return step_st<ST_F32>(tx, d, nslots, tiles, parity, idx, s, variant);
+    case ST_F16S: return step_st<ST_F16S>(tx, d, nslots, tiles, parity, idx, s, variant);
+    case ST_BF16S: return step_st<ST_BF16S>(tx, d, nslots, tiles, parity, idx, s, variant);
     }
     return hipErrorInvalidValue;
 }

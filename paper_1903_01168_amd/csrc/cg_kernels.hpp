@@ -5,11 +5,18 @@
 
 namespace cgd {
 
-// nsc: launch the variant that carries the Navier-Stokes correction (Sec.
-// 2.1.3); it applies the correction to the lattices whose descriptor has
-// F_NSC and steps the others as the plain variant does
+// Variants of the step kernel: KV_NSC carries the Navier-Stokes correction
+// (Sec. 2.1.3; applied to the lattices whose descriptor has F_NSC, the others
+// are stepped as by the plain variant), KV_ISO the second-neighbour colour
+// gradient for every lattice of the launch.
+enum : int { KV_NSC = 1, KV_ISO = 2 };
+// The variant a lattice needs alone.
+inline int step_variant(const SlotDesc &d)
+{
+    return ((d.flags & F_NSC) ? KV_NSC : 0) | ((d.flags & F_ISO) ? KV_ISO : 0);
+}
 hipError_t launch_step(int storage, int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx,
-                       hipStream_t s, bool nsc);
+                       hipStream_t s, int variant);
 hipError_t launch_init(int storage, const SlotDesc *d, long long nodes, const float *fields, int which,
                        hipStream_t s);
 int moments_blocks(long long nodes);

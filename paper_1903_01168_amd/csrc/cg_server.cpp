@@ -132,7 +132,7 @@ struct GpuBackend : Backend {
     struct Chunk {
         hipGraphExec_t graph = nullptr;
         int off = -1, nslots = -1, tiles = -1, K = -1;
-        bool nsc = false;
+        int variant = 0;
     };
     std::vector<Chunk> chunks;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -200,12 +200,12 @@ struct GpuBackend : Backend {
         std::vector<char> kind;
         for (auto *r : act) {
             bytes.push_back(2 * r->ctx->buf_bytes);
-            kind.push_back(r->ctx->p.ns_correction != 0);
+            kind.push_back((char)cgd::step_variant(r->ctx->desc));
         }
         const std::vector<int> first = cgi::cache_groups(bytes, kind);
         const int ng = (int)first.size() - 1;
         std::vector<int> gtiles(ng, 0);
-        std::vector<char> gnsc(ng, 0);     // the group needs the Navier-Stokes variant
+        std::vector<int> gvar(ng, 0);      // the group's step-kernel variant
         for (int g = 0; g < ng; ++g) {
             long long tiles = 0, nodes = 0;
             for (int i = first[g]; i < first[g + 1]; ++i) nodes += act[i]->nodes();
@@ -219,7 +219,7 @@ struct GpuBackend : Backend {
                 d.active_steps = (int)std::min<int64_t>(K, r->steps - r->done);
                 if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // launch 0 reads the current buffer
                 tiles += (long long)d.tiles_x * d.tiles_y;
-                if (d.flags & cgd::F_NSC) gnsc[g] = 1;
+                gvar[g] = cgd::step_variant(d);
                 table.push_back(d);
             }
             if (tiles > INT_MAX / 2) {
@@ -234,20 +234,20 @@ struct GpuBackend : Backend {
         for (int g = 0; g < ng && e == hipSuccess; ++g) {
             Chunk &ch = chunks[g];
             const int off = first[g], ns = first[g + 1] - first[g], nt = gtiles[g];
-            const bool nsc = gnsc[g] != 0;
-            if (ch.off != off || ch.nslots != ns || ch.tiles != nt || ch.K != K || ch.nsc != nsc) {
+            const int var = gvar[g];
+            if (ch.off != off || ch.nslots != ns || ch.tiles != nt || ch.K != K || ch.variant != var) {
                 if (ch.graph) (void)hipGraphExecDestroy(ch.graph);
                 ch = Chunk{};
                 hipGraph_t gr = nullptr;
                 e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
                 hipError_t le = hipSuccess;
                 for (int j = 0; j < K && e == hipSuccess && le == hipSuccess; ++j)
-                    le = cgd::launch_step(storage, tx, d_slots + off, ns, nt, j & 1, j, cap, nsc);
+                    le = cgd::launch_step(storage, tx, d_slots + off, ns, nt, j & 1, j, cap, var);
                 if (e == hipSuccess) e = hipStreamEndCapture(cap, &gr);
                 if (e == hipSuccess) e = le;
                 if (e == hipSuccess) e = hipGraphInstantiate(&ch.graph, gr, nullptr, nullptr, 0);
                 if (gr) (void)hipGraphDestroy(gr);
-                if (e == hipSuccess) ch = Chunk{ch.graph, off, ns, nt, K, nsc};
+                if (e == hipSuccess) ch = Chunk{ch.graph, off, ns, nt, K, var};
                 else ch = Chunk{};
             }
             if (e == hipSuccess) e = hipGraphLaunch(ch.graph, stream);

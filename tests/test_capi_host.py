@@ -124,3 +124,12 @@ def test_ns_correction_fields_validated(lib):
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
     cp.ns_correction, cp.reserved1 = 1, 1
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
+
+
+def test_gradient_field_validated(lib):
+    cp = capi.make_params(W.params(nx=16, ny=8, A=1e-3, gradient="isotropic"))
+    assert cp.gradient == 1 and lib.lbm_bytes_required(C.byref(cp)) > 0
+    cp.gradient = 2
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
+    cp.gradient, cp.reserved2 = 1, 3
+    assert lib.lbm_bytes_required(C.byref(cp)) == 0
