@@ -133,3 +133,27 @@ def test_gradient_field_validated(lib):
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
     cp.gradient, cp.reserved2 = 1, 3
     assert lib.lbm_bytes_required(C.byref(cp)) == 0
+
+
+def test_header_is_c99_and_structs_match_the_binding(tmp_path):
+    """The public headers compile as plain C99, and the ctypes mirrors of
+    their structs have the C layout (size and every field offset)."""
+    from paper_1903_01168_amd import serve
+    mirrors = [("lbm_params", capi.LbmParams), ("lbm_diag_t", capi.LbmDiag), ("lbm_init_desc", serve.InitDesc),
+               ("lbm_result", serve.Result), ("lbm_server_stats", serve.Stats)]
+    body = []
+    for cname, py in mirrors:
+        body.append(f'  printf("%zu\\n", sizeof({cname}));\n')
+        body += [f'  printf("%zu\\n", offsetof({cname}, {f}));\n' for f, _ in py._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "cglbm.h"\n#include "cglbm_serve.h"\n'
+                   "int main(void) {\n" + "".join(body) + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                    os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = []
+    for _, py in mirrors:
+        want.append(C.sizeof(py))
+        want += [getattr(py, f).offset for f, _ in py._fields_]
+    assert out == want
