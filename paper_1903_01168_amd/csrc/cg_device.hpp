@@ -782,9 +782,14 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
     const float uu = ux * ux + uy * uy;
 
     float neq[9];     // N - N^(e)
-    float G[9];       // Guo forcing source (force density rho g)
     const bool force = S.flags & F_FORCE;
     const float gxr = rho * S.gx, gyr = rho * S.gy;
+    // Guo forcing source of direction i (force density rho g); evaluated only
+    // under the uniform branch of a forced lattice
+    auto guo = [&](int i) {
+        const float cu = cx(i) * ux + cy(i) * uy;
+        return wgt(i) * ((3.f * (cx(i) - ux) + 9.f * cu * cx(i)) * gxr + (3.f * (cy(i) - uy) + 9.f * cu * cy(i)) * gyr);
+    };
     // Hermite equilibrium: the linear term of colour k carries the factor
     // 1 + (3 c_s,k^2 - 1)(3 |c_i|^2 - 4) / 2; summed over the colours its
     // density is rho + hco(i) K with K = sum_k rho_k (3 c_s,k^2 - 1)
@@ -804,20 +809,25 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
             neq[i] = t - wgt(i) * (3.f * cu * __builtin_fmaf(hco(i), K, rho) + rho * (4.5f * cu * cu - 1.5f * uu));
         else
             neq[i] = t - rho * wgt(i) * (3.f * cu + 4.5f * cu * cu - 1.5f * uu);
-        G[i] = force ? wgt(i) * ((3.f * (cx(i) - ux) + 9.f * cu * cx(i)) * gxr +
-                                 (3.f * (cy(i) - uy) + 9.f * cu * cy(i)) * gyr)
-                     : 0.f;
     }
     float ns[9];
     if (S.flags & F_MRT) {
-        float m[9], mg[9], q[9];
+        float m[9], q[9];
         mrt_fwd(neq, m);
-        if (force) mrt_fwd(G, mg);
         const float sl = S.mrt_lambda * w;
+        if (force) {
+            float G[9], mg[9];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            const float s = (j >= 7) ? w : sl;
-            q[j] = s * m[j] - (force ? (1.f - 0.5f * s) * mg[j] : 0.f);
+            for (int i = 0; i < 9; ++i) G[i] = guo(i);
+            mrt_fwd(G, mg);
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                const float s = (j >= 7) ? w : sl;
+                q[j] = s * m[j] - (1.f - 0.5f * s) * mg[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 9; ++j) q[j] = ((j >= 7) ? w : sl) * m[j];
         }
         if (herm) {
             // source U = M^-1 C, C_1 = 3 (1 - s_1/2)(dQx/dx + dQy/dy),
@@ -830,9 +840,14 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
 #pragma unroll
         for (int i = 0; i < 9; ++i) ns[i] = nd.n[i] - dn[i];
     } else {
-        const float hf = 1.f - 0.5f * w;
+        if (force) {
+            const float hf = 1.f - 0.5f * w;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) ns[i] = __builtin_fmaf(hf, G[i], __builtin_fmaf(-w, neq[i], nd.n[i]));
+            for (int i = 0; i < 9; ++i) ns[i] = __builtin_fmaf(hf, guo(i), __builtin_fmaf(-w, neq[i], nd.n[i]));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) ns[i] = __builtin_fmaf(-w, neq[i], nd.n[i]);
+        }
     }
 
     const float F2 = Fx * Fx + Fy * Fy;

@@ -154,9 +154,11 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
         // Second-neighbour colour gradient: 25 points, isotropic to 8th
         // order (weights w(|c|^2): 4/21, 4/45, 1/60, 2/315, 1/5040 for
         // |c|^2 = 1, 2, 4, 5, 8).  The colour field of rows y-2d .. y+2d
-        // lives in registers, per row its value and the lane values one and
-        // two columns east and west; the populations of row y+3d are
-        // requested before row y collides, rows y+d and y+2d are complete.
+        // lives in registers, one value per lane and row; the lane values one
+        // and two columns east and west are fetched by DPP shifts each time a
+        // row is used (fewer registers than keeping them), by every lane
+        // before any lane branches.  The populations of row y+3d are
+        // requested before row y collides; rows y+d and y+2d are complete.
         struct Psi5 {
             float c, e1, w1, e2, w2;
         };
@@ -167,10 +169,11 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
         // ghost row next to a wall from the adjacent real row (the rule of
         // ghost()); lanes two columns beyond an open face, which no fluid
         // node neighbours, take the inner ghost column's value
-        auto ghost5 = [&](const Psi5 &f) -> Psi5 {
-            const float g = ((in0 ? 4.f * f.c : 0.f) + (inw ? f.w1 : 0.f) + (ine ? f.e1 : 0.f)) * ginv;
+        auto ghost1 = [&](float c) -> float {
+            const float e1 = from_east(c), w1 = from_west(c);
+            const float g = ((in0 ? 4.f * c : 0.f) + (inw ? w1 : 0.f) + (ine ? e1 : 0.f)) * ginv;
             const float ge = from_east(g), gw = from_west(g);
-            return psi5(gden > 0.f ? g : (xl < 0 ? ge : gw));
+            return gden > 0.f ? g : (xl < 0 ? ge : gw);
         };
         // Rows at the same distance ahead and behind enter as sums (x) or
         // differences (y) before any weight multiplies them, so that the
@@ -182,7 +185,7 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
         auto sx2 = [](const Psi5 &p) { return p.e2 + p.w2; };
         auto wanted = [&](int r) { return (d > 0 ? r <= y1 + 1 : r >= y0 - 2) && gathered(r); };
 
-        Psi5 pb2, pb1, p0, pa1;                // rows y-2d, y-d, y, y+d
+        float cb2, cb1, c0, ca1;               // colour field of rows y-2d, y-d, y, y+d
         QRow qb{}, q0{}, qa{};                 // Q partial sums of rows y-d, y, y+d (NSC)
         Node cur, nxt;                         // rows y and y+d
         {
@@ -197,28 +200,28 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
             const Raw18<ST> r0 = issue<ST>(S, src, xc, w0);
             if (ha1) ra1 = issue<ST>(S, src, xc, wa1);
             cur = finish<ST>(S, r0, xc, w0);
-            p0 = psi5(color_field(S, cur.rr, cur.rb));
+            c0 = color_field(S, cur.rr, cur.rb);
             if (nsc) q0 = qreal(cur);
             if (hb1) {
                 const Node t = finish<ST>(S, rb1, xc, wb1);
-                pb1 = psi5(color_field(S, t.rr, t.rb));
+                cb1 = color_field(S, t.rr, t.rb);
                 if (nsc) qb = qreal(t);
             } else {
-                pb1 = ghost5(p0);
+                cb1 = ghost1(c0);
                 if (nsc) qb = qghost(cur);
             }
             if (hb2) {
                 const Node t = finish<ST>(S, rb2, xc, wb2);
-                pb2 = psi5(color_field(S, t.rr, t.rb));
+                cb2 = color_field(S, t.rr, t.rb);
             } else {
-                pb2 = hb1 ? ghost5(pb1) : pb1;   // beyond a wall: distance 1, or the inner ghost row
+                cb2 = hb1 ? ghost1(cb1) : cb1;   // beyond a wall: distance 1, or the inner ghost row
             }
             if (ha1) {
                 nxt = finish<ST>(S, ra1, xc, wa1);
-                pa1 = psi5(color_field(S, nxt.rr, nxt.rb));
+                ca1 = color_field(S, nxt.rr, nxt.rb);
                 if (nsc) qa = qreal(nxt);
             } else {
-                pa1 = ghost5(p0);
+                ca1 = ghost1(c0);
                 if (nsc) qa = qghost(cur);
             }
         }
@@ -230,20 +233,21 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
         const float fd = (float)d;
         for (int y = ys; y != ye; y += d) {
             Node nn;                           // row y+2d
-            Psi5 pa2;
+            float ca2;
             QRow q2{};
             if (hp) {
                 nn = finish<ST>(S, pend, xc, make_row<ST>(S, real_row(y + 2 * d)));
-                pa2 = psi5(color_field(S, nn.rr, nn.rb));
+                ca2 = color_field(S, nn.rr, nn.rb);
                 if (nsc) q2 = qreal(nn);
             } else if (gathered(y + d)) {       // row y+2d is the ghost row next to a wall
-                pa2 = ghost5(pa1);
+                ca2 = ghost1(ca1);
                 if (nsc) q2 = qghost(nxt);
             } else {                           // two rows beyond a wall: the inner ghost row
-                pa2 = pa1;
+                ca2 = ca1;
             }
             hp = wanted(y + 3 * d);
             if (hp) pend = issue<ST>(S, src, xc, make_row<ST>(S, real_row(y + 3 * d)));
+            const Psi5 pb2 = psi5(cb2), pb1 = psi5(cb1), p0 = psi5(c0), pa1 = psi5(ca1), pa2 = psi5(ca2);
             if (out_lane) {
                 // F_x = sum over rows dy of w(1+dy^2) (psi(+1) - psi(-1)) + 2 w(4+dy^2) (psi(+2) - psi(-2));
                 // F_y = sum over rows of dy [w(dy^2) psi(0) + w(1+dy^2) (psi(+1) + psi(-1))
@@ -260,17 +264,17 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
                 if constexpr (NSC) {
                     const float dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
                     const float dqy = fd * (qa.s - qb.s);
-                    collide<true>(S, cur, p0.c, Fx, Fy, outr, outb, nsc, dqx, dqy);
+                    collide<true>(S, cur, c0, Fx, Fy, outr, outb, nsc, dqx, dqy);
                 } else {
-                    collide(S, cur, p0.c, Fx, Fy, outr, outb);
+                    collide(S, cur, c0, Fx, Fy, outr, outb);
                 }
                 if (ST == ST_F32) conserve(cur, outr, outb);
                 store18<ST>(S, dst, xc.o0, (uint32_t)y * rowbytes, outr, outb, cur.mr, cur.mb);
             }
-            pb2 = pb1;
-            pb1 = p0;
-            p0 = pa1;
-            pa1 = pa2;
+            cb2 = cb1;
+            cb1 = c0;
+            c0 = ca1;
+            ca1 = ca2;
             qb = q0;
             q0 = qa;
             qa = q2;
