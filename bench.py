@@ -379,7 +379,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the step runs on one GPU: there is no multi-GPU path to measure "
+                                   "(how a lattice would be split into slabs is described in the design notes)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
