@@ -92,3 +92,25 @@ def test_16bit_against_fp32(storage):
         assert b["n_nonfinite"] == 0
         assert abs(b["mass_r"] / mr - 1) <= 1e-7 and abs(b["mass_b"] / mb - 1) <= 1e-7
         assert b["max_u"] <= 1.5 * a["max_u"] + 1e-5
+
+
+@pytest.mark.parametrize("variant", ["isotropic", "mrt_nsc"])
+def test_c1_laplace_variants(variant):
+    """The converged 64 x 64 bubble with the second-neighbour gradient, and
+    with MRT and the Navier-Stokes correction: every storage's pressure jump
+    within 1% of the FP64 oracle's for the same variant, colour mass within
+    1e-7."""
+    c = W.static_bubble(n=64, radius=16)
+    p = dict(c["params"], gradient="isotropic") if variant == "isotropic" else \
+        dict(c["params"], collision="mrt", ns_correction=True)
+    s = oracle.Sim(**p).init(c["rho_r"], c["rho_b"], None, None)
+    s.step(20000)
+    dp64, R = _laplace_fields(s.moments(), p, 64)
+    mr, mb = c["rho_r"].sum(), c["rho_b"].sum()
+    for storage in ("f32", "f16s", "bf16s"):
+        d = _gpu(p, c, 20000, storage)
+        dp = d["p_in"] - d["p_out"]
+        say(f"C1 {variant} {storage}: dp rel. to FP64 {dp / dp64 - 1:+.2e} (FP64 dp / (sigma/R) = "
+            f"{dp64 / (4e-3 / 9 / R):.4f}), mass drift {d['mass_r'] / mr - 1:+.1e} {d['mass_b'] / mb - 1:+.1e}")
+        assert abs(dp / dp64 - 1) <= 0.01
+        assert abs(d["mass_r"] / mr - 1) <= 1e-7 and abs(d["mass_b"] / mb - 1) <= 1e-7
