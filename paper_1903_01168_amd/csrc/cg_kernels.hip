@@ -63,8 +63,8 @@ __device__ __forceinline__ Psi3 psi3(float c) { return Psi3{from_west(c), c, fro
 // the adjacent lanes, and the populations of row y+2 are requested before row
 // y collides.
 template <int ST, int W, bool NSC, bool ISO>
-__global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
-                                                 int parity, int launch_idx)
+__device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
+                                          int parity, int launch_idx)
 {
     const int tile = xcd_tile(blockIdx.x, total_tiles);
     const SlotDesc S = slots[find_slot(slots, nslots, tile)];
@@ -359,6 +359,24 @@ __global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ sl
     }
 }
 
+template <int ST, int W, bool NSC, bool ISO>
+__global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
+                                                 int parity, int launch_idx)
+{
+    step_body<ST, W, NSC, ISO>(slots, nslots, total_tiles, parity, launch_idx);
+}
+
+// The FP32 second-neighbour variant without the correction, its register
+// budget capped at 4 waves per SIMD (128 VGPRs, reached without spilling):
+// 9% faster than at the 3 waves its natural allocation allows.  The 16-bit
+// and corrected variants would spill to scratch under the same cap.
+template <int ST, int W>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_step_iso4(const SlotDesc *__restrict__ slots, int nslots, int total_tiles, int parity, int launch_idx)
+{
+    step_body<ST, W, false, true>(slots, nslots, total_tiles, parity, launch_idx);
+}
+
 // ---------------------------------------------------------------- init --
 template <int ST>
 __global__ void __launch_bounds__(256) k_init(const SlotDesc *__restrict__ sd, const float *__restrict__ f,
@@ -549,11 +567,20 @@ __global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uin
 template <int ST, bool NSC, bool ISO>
 static hipError_t step_v(int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx, hipStream_t s)
 {
-    switch (tx) {
-    case 64: hipLaunchKernelGGL((k_step<ST, 1, NSC, ISO>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
-    case 128: hipLaunchKernelGGL((k_step<ST, 2, NSC, ISO>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
-    case 256: hipLaunchKernelGGL((k_step<ST, 4, NSC, ISO>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
-    default: return hipErrorInvalidValue;
+    if constexpr (ST == ST_F32 && ISO && !NSC) {
+        switch (tx) {
+        case 64: hipLaunchKernelGGL((k_step_iso4<ST, 1>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
+        case 128: hipLaunchKernelGGL((k_step_iso4<ST, 2>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
+        case 256: hipLaunchKernelGGL((k_step_iso4<ST, 4>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (tx) {
+        case 64: hipLaunchKernelGGL((k_step<ST, 1, NSC, ISO>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
+        case 128: hipLaunchKernelGGL((k_step<ST, 2, NSC, ISO>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
+        case 256: hipLaunchKernelGGL((k_step<ST, 4, NSC, ISO>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
