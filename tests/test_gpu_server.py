@@ -41,6 +41,11 @@ def _cases(storage):
                      None))
     d = W.wall_droplet(120.0, n=64, storage=storage)
     cases.append((d["params"], serve.init_fields(d["rho_r"], d["rho_b"]), 222, d["rho_r"], d["rho_b"], None))
+    # and one with the second-neighbour gradient (another kernel variant and tile width)
+    c = W.bubble_cell(10.0, 10, 20, n=80, storage=storage)
+    c["params"]["gradient"] = "isotropic"
+    cases.insert(1, (c["params"], serve.init_disk(40, 40, 20, 1.0, 0.0, 0.0, 10.0), 130, c["rho_r"], c["rho_b"],
+                     None))
     return cases
 
 
