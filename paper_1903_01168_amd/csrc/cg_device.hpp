@@ -358,6 +358,19 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+// The same for v within three periods of [0, n) (row indices of the gather
+// window, at most 3 rows outside the lattice): additions instead of a
+// division in the row loop.
+__device__ __forceinline__ int wrap_near(int v, int n)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v = v < 0 ? v + n : v;
+        v = v >= n ? v - n : v;
+    }
+    return v;
+}
+
 template <int ST>
 __device__ __forceinline__ XCols make_cols(const SlotDesc &S, int x)
 {
@@ -399,7 +412,7 @@ __device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y)
     for (int d = -1; d <= 1; ++d) {       // d = c_y
         int sy = y - d;
         const bool out = sy < 0 || sy >= S.ny;
-        if (out && per) sy = wrapi(sy, S.ny);
+        if (out && per) sy = wrap_near(sy, S.ny);
         r.off[d + 1] = (uint32_t)((out && !per) ? y : sy) * (uint32_t)S.pitch * Codec<ST>::bytes;
     }
     return r;

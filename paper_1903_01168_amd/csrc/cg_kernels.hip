@@ -105,7 +105,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         const float g = ((in0 ? 4.f * f.c : 0.f) + (inw ? f.w : 0.f) + (ine ? f.e : 0.f)) * ginv;
         return psi3(g);
     };
-    auto real_row = [&](int r) { return yper ? wrapi(r, ny) : r; };
+    auto real_row = [&](int r) { return yper ? wrap_near(r, ny) : r; };
     auto gathered = [&](int r) { return yper || (r >= 0 && r < ny); };
 
     // Navier-Stokes correction (Sec. 2.1.3): Q = sum_k (1.8 alpha_k - 0.8)
