@@ -15,6 +15,14 @@ from paper_1903_01168_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
+# FP32 populations keep colour mass only up to rounding: the FP64 oracle whose
+# populations are rounded to FP32 after every step drifts by 1.1e-6 (nearest
+# gradient) and 3.3e-6 (isotropic gradient) in 20000 steps of this bubble; the
+# GPU's FP32 step drifts less (measured up to 1.6e-7), and this bound keeps it
+# below both.
+FP32_MASS = 1e-6
+
+
 def say(*a):
     print("[gpu-precision]", *a, file=sys.stderr, flush=True)
 
@@ -65,7 +73,8 @@ def test_c1_laplace_against_fp64(c1_fp64, storage):
     say(f"C1 {storage}: dp rel. to FP64 {dp / dp64 - 1:+.2e}, mass drift {d['mass_r'] / mr - 1:+.1e} "
         f"{d['mass_b'] / mb - 1:+.1e}, max|u| {d['max_u']:.2e}")
     assert abs(dp / dp64 - 1) <= 0.01
-    assert abs(d["mass_r"] / mr - 1) <= 1e-7 and abs(d["mass_b"] / mb - 1) <= 1e-7
+    bound = FP32_MASS if storage == "f32" else 1e-7
+    assert abs(d["mass_r"] / mr - 1) <= bound and abs(d["mass_b"] / mb - 1) <= bound
     assert d["max_u"] <= 2e-5          # FP64: 5e-6
 
 
@@ -99,7 +108,8 @@ def test_c1_laplace_variants(variant):
     """The converged 64 x 64 bubble with the second-neighbour gradient, and
     with MRT and the Navier-Stokes correction: every storage's pressure jump
     within 1% of the FP64 oracle's for the same variant, colour mass within
-    1e-7."""
+    1e-7 for the 16-bit storages (exact colour-mass bookkeeping) and within
+    FP32_MASS for FP32."""
     c = W.static_bubble(n=64, radius=16)
     p = dict(c["params"], gradient="isotropic") if variant == "isotropic" else \
         dict(c["params"], collision="mrt", ns_correction=True)
@@ -113,4 +123,5 @@ def test_c1_laplace_variants(variant):
         say(f"C1 {variant} {storage}: dp rel. to FP64 {dp / dp64 - 1:+.2e} (FP64 dp / (sigma/R) = "
             f"{dp64 / (4e-3 / 9 / R):.4f}), mass drift {d['mass_r'] / mr - 1:+.1e} {d['mass_b'] / mb - 1:+.1e}")
         assert abs(dp / dp64 - 1) <= 0.01
-        assert abs(d["mass_r"] / mr - 1) <= 1e-7 and abs(d["mass_b"] / mb - 1) <= 1e-7
+        bound = FP32_MASS if storage == "f32" else 1e-7
+        assert abs(d["mass_r"] / mr - 1) <= bound and abs(d["mass_b"] / mb - 1) <= bound
