@@ -461,8 +461,10 @@ def main():
     mlups = nodes * args.steps / (ms / 1e3) / 1e6
 
     bpu = bytes_per_update(args.storage)
-    # algorithmic bytes over kernel time; a step is `launches` launches (one per
-    # cache-sized group of lattices), so this is also the launch-weighted mean
+    # algorithmic bytes of a step over the step's time: a step is `launches`
+    # launches (one per group of lattices), two of them in flight at a time
+    # when there are several, so the step's time is the union of the kernels'
+    # busy intervals
     achieved = bpu * nodes / (ms_per_step / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -509,8 +511,10 @@ def main():
                    "nodes": nodes, "storage": args.storage, "collision": args.collision,
                    "ns_correction": bool(args.ns_correction), "gradient": args.gradient,
                    "steps_simulated": args.warmup + args.steps, "seed": args.seed,
-                   "launch": f"batched k_step, {launches} launch(es) per step (lattices grouped to fit the "
-                             "Infinity Cache, groups in turns of 256 steps), HIP-graph replay of 32 steps"},
+                   "launch": (f"batched k_step, {launches} launches per step: lattices in groups sized so that "
+                              "two fit the Infinity Cache together, two groups in flight on two streams (rounds "
+                              "of 256 steps per group), HIP-graph replay of 32 steps" if launches > 1 else
+                              "batched k_step, one launch per step, HIP-graph replay of 32 steps")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_update": bpu, "kernel": "k_step", "launches_per_step": launches,

@@ -196,12 +196,17 @@ int lbm_set_launch(lbm_ctx *ctx, int32_t tile_x, int32_t strip_rows);
 void *lbm_stream(const lbm_ctx *ctx);
 
 /* ---- batched stepping -------------------------------------------------
- * A batch advances several contexts (same device, same storage type) with ONE
- * kernel launch per time step: every workgroup finds its lattice in a device
- * table of lattice descriptors.  When the contexts' buffers together exceed
- * the last-level cache budget (192 MiB of MI355X's 256 MB Infinity Cache) the
- * batch is split into groups that fit, balanced by bytes, and lbm_batch_step
- * advances the groups in turns of 256 steps (each group one launch per step);
+ * A batch advances several contexts (same device, same storage type) with one
+ * kernel launch per group of lattices and time step: every workgroup finds
+ * its lattice in a device table of lattice descriptors.  A batch of two or more lattices is split
+ * into groups (contiguous, balanced by bytes, at least two, never mixing
+ * kernel variants) sized so that two groups fit MI355X's 256 MB Infinity
+ * Cache together (240 MiB), and lbm_batch_step advances two groups at a time
+ * on two streams of its own (rounds of 256 steps per group, the work of a
+ * round halved between the streams; one group's launch then fills the chip
+ * while the other's last wavefronts finish).  The streams start after the
+ * work already queued on hip_stream and on the contexts' streams, and those
+ * streams wait for them at the end of the call (no host synchronisation);
  * after the call every context has advanced n steps.  Each lattice's
  * arithmetic is exactly that of lbm_step, so results are bit-identical to
  * stepping the contexts one by one, in any grouping.  The contexts must not

@@ -212,7 +212,7 @@ static int wave_tiles(int nx, bool iso)
     return (nx + cols - 1) / cols;
 }
 
-int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req)
+int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool paired)
 {
     if (req > 0) return req < ny ? req : ny;
     // A wavefront marches through its strip row by row, each row a dependent
@@ -228,23 +228,25 @@ int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req)
     // wavefronts as the chip holds at once (256 CUs x 4 SIMDs x 4 waves at the
     // step kernel's register count): there they beat 2-4 rows by 1.4-9% in
     // both storages (slug, sweep groups) while neither filling the chip too
-    // thinly nor leaving a short last wave.
+    // thinly nor leaving a short last wave.  Two launches in flight together
+    // (`nodes` then counts both): FP32 8 rows, 1-3% ahead of 6 with each
+    // kernel variant on the sweep; 16-bit storage stays at 6.
     int s;
     if (nodes <= (1LL << 17)) s = 1;
-    else if (nodes >= 1000000LL && nodes <= 3000000LL) s = 6;
+    else if (nodes >= 1000000LL && nodes <= 3000000LL) s = paired && storage == LBM_STORE_F32 ? 8 : 6;
     else if (nodes <= 1500000LL) s = 2;
     else if (storage == LBM_STORE_F32) s = tiles_x >= 16 ? 4 : 8;
     else s = nodes <= 3000000LL ? 4 : 8;
     return ny < s ? ny : s;
 }
 
-std::vector<int> cache_groups(const std::vector<size_t> &bytes)
+std::vector<int> cache_groups(const std::vector<size_t> &bytes, size_t budget, int min_groups)
 {
     const int n = (int)bytes.size();
     size_t total = 0;
     for (size_t b : bytes) total += b;
-    const int ng = (int)std::min<size_t>((size_t)std::max(n, 1),
-                                         std::max<size_t>(1, (total + kCacheBudget - 1) / kCacheBudget));
+    const size_t want = std::max<size_t>((size_t)std::max(min_groups, 1), (total + budget - 1) / budget);
+    const int ng = (int)std::min<size_t>((size_t)std::max(n, 1), want);
     std::vector<int> first(1, 0);
     size_t acc = 0;
     for (int i = 0, g = 1; i + 1 < n && g < ng; ++i) {
@@ -258,14 +260,16 @@ std::vector<int> cache_groups(const std::vector<size_t> &bytes)
     return first;
 }
 
-std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind)
+std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind, size_t budget,
+                              int min_groups)
 {
     std::vector<int> first(1, 0);
     const int n = (int)bytes.size();
     for (int a = 0; a < n;) {
         int e = a + 1;
         while (e < n && kind[e] == kind[a]) ++e;
-        const std::vector<int> f = cache_groups(std::vector<size_t>(bytes.begin() + a, bytes.begin() + e));
+        const std::vector<int> f =
+            cache_groups(std::vector<size_t>(bytes.begin() + a, bytes.begin() + e), budget, min_groups);
         for (size_t j = 1; j < f.size(); ++j) first.push_back(a + f[j]);
         a = e;
     }
@@ -716,6 +720,7 @@ struct BatchGroup {
     std::vector<SlotDesc> slots;
     SlotDesc *d_slots = nullptr;
     int tiles = 0;
+    long long nodes = 0;
     int variant = 0;                    // step-kernel variant of its lattices (one per group)
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
@@ -726,6 +731,11 @@ struct lbm_batch {
     std::vector<BatchGroup> groups;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    // two or more groups: two lanes (streams) step two groups at a time;
+    // ev_join orders the batch stream and the contexts' streams around them
+    hipStream_t lane[2] = {nullptr, nullptr};
+    hipEvent_t ev_join = nullptr, ev_split = nullptr, ev_lane[2] = {nullptr, nullptr};
+    std::vector<hipStream_t> ctx_streams;   // distinct streams of the contexts
     int device = 0, storage = 0, tx = 0;
     int64_t steps = 0;
     std::string err;
@@ -746,12 +756,18 @@ int lbm_batch_destroy(lbm_batch *b)
     if (!b) return LBM_OK;
     DeviceGuard g(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (hipStream_t l : b->lane)
+        if (l) (void)hipStreamSynchronize(l);
     for (auto &G : b->groups) {
         for (auto &x : G.graph)
             if (x) (void)hipGraphExecDestroy(x);
         if (G.d_slots) (void)hipFree(G.d_slots);
     }
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (hipStream_t l : b->lane)
+        if (l) (void)hipStreamDestroy(l);
+    for (hipEvent_t ev : {b->ev_join, b->ev_split, b->ev_lane[0], b->ev_lane[1]})
+        if (ev) (void)hipEventDestroy(ev);
     delete b;
     return LBM_OK;
 }
@@ -786,17 +802,33 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
         bytes.push_back(2 * ctxs[i]->buf_bytes);
         kind.push_back((char)cgd::step_variant(ctxs[i]->desc));
     }
-    const std::vector<int> first = cache_groups(bytes, kind);
-    b->groups.resize(first.size() - 1);
-    for (size_t gi = 0; gi + 1 < first.size(); ++gi) {
+    const std::vector<int> first = cache_groups(bytes, kind, kPairBudget / 2, 2);
+    const int ngroups = (int)first.size() - 1;
+    b->groups.resize(ngroups);
+    // strips are planned for what shares the chip: the group, and the group
+    // the other lane steps beside it (two groups of the batch at a time)
+    long long pair_nodes = 0;
+    {
+        std::vector<long long> gn;
+        for (int gi = 0; gi < ngroups; ++gi) {
+            long long nodes = 0;
+            for (int i = first[gi]; i < first[gi + 1]; ++i) nodes += (long long)ctxs[i]->p.nx * ctxs[i]->p.ny;
+            gn.push_back(nodes);
+        }
+        std::sort(gn.begin(), gn.end());
+        pair_nodes = gn.back() + (ngroups > 1 ? gn[ngroups - 2] : 0);
+    }
+    for (int gi = 0; gi < ngroups; ++gi) {
         BatchGroup &G = b->groups[gi];
         long long tiles = 0, nodes = 0;
         for (int i = first[gi]; i < first[gi + 1]; ++i) nodes += (long long)ctxs[i]->p.nx * ctxs[i]->p.ny;
+        G.nodes = nodes;
         for (int i = first[gi]; i < first[gi + 1]; ++i) {
             lbm_ctx *c = ctxs[i];
             SlotDesc d = c->desc;
             set_geometry(d, &c->p, c->lay, tx, 1);
-            set_geometry(d, &c->p, c->lay, tx, plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, c->strip_req));
+            set_geometry(d, &c->p, c->lay, tx,
+                         plan_strip(pair_nodes, c->p.ny, d.tiles_x, c->p.storage, c->strip_req, ngroups > 1));
             d.tile_begin = (int)tiles;
             d.active_steps = INT_MAX;
             if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer
@@ -821,6 +853,19 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
         lbm_batch_destroy(b);
         return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
     }
+    if (ngroups > 1) {
+        for (hipStream_t &l : b->lane)
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&l, hipStreamNonBlocking);
+        for (hipEvent_t *ev : {&b->ev_join, &b->ev_split, &b->ev_lane[0], &b->ev_lane[1]})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            lbm_batch_destroy(b);
+            return fail(nullptr, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+        }
+    }
+    for (auto *c : b->ctx)
+        if (std::find(b->ctx_streams.begin(), b->ctx_streams.end(), c->stream) == b->ctx_streams.end())
+            b->ctx_streams.push_back(c->stream);
     for (auto &G : b->groups)
         if ((e = hipMalloc(&G.d_slots, G.slots.size() * sizeof(SlotDesc))) != hipSuccess) {
             G.d_slots = nullptr;
@@ -865,7 +910,7 @@ static int batch_graph(lbm_batch *b, BatchGroup &G, int parity)
 
 // n steps of one group, starting at batch step `start` (graph replays, then
 // single launches)
-static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n)
+static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n, hipStream_t stream)
 {
     int64_t t = start;
     while (n >= 2 * kGraphSteps || (n >= kGraphSteps && n % kGraphSteps == 0)) {
@@ -874,14 +919,14 @@ static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n)
             int rc = batch_graph(b, G, par);
             if (rc != LBM_OK) return rc;
         }
-        hipError_t e = hipGraphLaunch(G.graph[par], b->stream);
+        hipError_t e = hipGraphLaunch(G.graph[par], stream);
         if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
         t += kGraphSteps;
         n -= kGraphSteps;
     }
     for (; n > 0; --n, ++t) {
         hipError_t e = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (int)(t & 1), 0,
-                                        b->stream, G.variant);
+                                        stream, G.variant);
         if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     }
     return LBM_OK;
@@ -897,18 +942,134 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
         if (b->ctx[i]->steps - b->base[i] != b->steps)
             return bfail(b, LBM_E_INVAL, "a context of the batch was stepped outside it");
     DeviceGuard g(b->device);
-    // one group: all steps at once; several: rounds of kRoundSteps per group
-    const int64_t round = b->groups.size() == 1 ? n : kRoundSteps;
+    if (b->groups.size() == 1) {
+        // one group: every step on the batch stream
+        const int rc = group_steps(b, b->groups[0], b->steps, n, b->stream);
+        if (rc != LBM_OK) return rc;
+        b->steps += n;
+        for (auto *c : b->ctx) c->steps += n;
+        return LBM_OK;
+    }
+    if (n == 0) return LBM_OK;
+    hipError_t e = hipSuccess;
+    // the lanes start after the work queued so far on the batch stream and on
+    // the contexts' streams (an event's wait takes its latest record)
+    for (hipStream_t s : b->ctx_streams) {
+        if (e == hipSuccess) e = hipEventRecord(b->ev_join, s);
+        for (hipStream_t l : b->lane)
+            if (e == hipSuccess) e = hipStreamWaitEvent(l, b->ev_join, 0);
+    }
+    if (e == hipSuccess && std::find(b->ctx_streams.begin(), b->ctx_streams.end(), b->stream) == b->ctx_streams.end()) {
+        e = hipEventRecord(b->ev_join, b->stream);
+        for (hipStream_t l : b->lane)
+            if (e == hipSuccess) e = hipStreamWaitEvent(l, b->ev_join, 0);
+    }
+    if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch fork: ") + hipGetErrorString(e));
+    // Rounds of kRoundSteps steps per group.  In a round the groups' work
+    // (nodes x steps) is cut into two halves, one per lane, in the order of
+    // the groups, wrapping around (McNaughton's schedule): lane 0 takes the
+    // first groups, lane 1 the last ones, and the group that straddles the
+    // cut makes its first steps at the start of lane 1 and its last steps at
+    // the end of lane 0, after an event.  At most two groups are in flight at
+    // any time, and the lanes finish a round together.  Where a group
+    // straddles the cut, each lane's next round waits for the other lane's
+    // end (the group may sit differently in a shorter last round).
+    bool first_round = true;
     while (n > 0) {
-        const int64_t k = std::min(n, round);
-        for (auto &G : b->groups) {
-            const int rc = group_steps(b, G, b->steps, k);
-            if (rc != LBM_OK) return rc;
+        const int64_t k = std::min(n, kRoundSteps);
+        const int ng = (int)b->groups.size();
+        double total = 0;
+        for (auto &G : b->groups) total += (double)G.nodes;
+        const double half = 0.5 * total;
+        int cut = ng;                    // the first group not wholly on lane 0
+        int64_t s1 = 0;                  // its steps on lane 1 (its first s1 steps)
+        bool straddle = false;           // it has a share of lane 0 as well
+        double acc = 0;
+        for (int gi = 0; gi < ng; ++gi) {
+            const double w = (double)b->groups[gi].nodes;
+            if (acc + w <= half * (1 + 1e-9)) {
+                acc += w;
+                continue;
+            }
+            cut = gi;
+            // lane 0 keeps the last (half - acc) / w of its k steps, in whole
+            // graph replays when the round is long enough for them
+            const double f0 = (half - acc) / w;
+            straddle = f0 > 1e-9;
+            int64_t on0 = (int64_t)std::llround(f0 * (double)k);
+            if (k >= 2 * kGraphSteps) on0 = (on0 + kGraphSteps / 2) / kGraphSteps * kGraphSteps;
+            on0 = std::max<int64_t>(0, std::min<int64_t>(k, on0));
+            s1 = k - on0;
+            break;
         }
+        const bool split = cut < ng && s1 > 0 && s1 < k;
+        const int64_t t0 = b->steps;
+        if (!first_round && straddle)
+            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lane[l], b->ev_lane[1 - l], 0);
+        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+        // the work of each lane: lane 1 the straddling group's first steps,
+        // then the groups after it; lane 0 the groups before the cut, then
+        // the straddling group's rest (after the event that ends its first
+        // steps)
+        struct Item {
+            int g;
+            int64_t start, steps;
+        };
+        std::vector<Item> work[2];
+        if (cut < ng && s1 > 0) work[1].push_back({cut, t0, s1});
+        for (int gi = cut + 1; gi < ng; ++gi) work[1].push_back({gi, t0, k});
+        for (int gi = 0; gi < std::min(cut, ng); ++gi) work[0].push_back({gi, t0, k});
+        if (cut < ng && s1 < k) work[0].push_back({cut, t0 + s1, k - s1});
+        // queued in turns of one graph replay per lane, so that both lanes
+        // have work from the start even when queueing is slower than the GPU
+        size_t pos[2] = {0, 0};
+        int64_t done[2] = {0, 0};
+        bool split_recorded = !split;
+        for (;;) {
+            bool progress = false, left = false;
+            for (int l = 1; l >= 0; --l) {
+                if (pos[l] >= work[l].size()) continue;
+                left = true;
+                const Item &it = work[l][pos[l]];
+                const bool rest = split && l == 0 && it.g == cut;
+                if (rest && !split_recorded) continue;            // its event is queued by lane 1 first
+                if (rest && done[l] == 0 && (e = hipStreamWaitEvent(b->lane[0], b->ev_split, 0)) != hipSuccess)
+                    return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+                const int64_t rem = it.steps - done[l];
+                const int64_t chunk = rem >= kGraphSteps ? kGraphSteps : rem;
+                const int rc = group_steps(b, b->groups[it.g], it.start + done[l], chunk, b->lane[l]);
+                if (rc != LBM_OK) return rc;
+                done[l] += chunk;
+                progress = true;
+                if (done[l] == it.steps) {
+                    if (split && l == 1 && it.g == cut) {
+                        if ((e = hipEventRecord(b->ev_split, b->lane[1])) != hipSuccess)
+                            return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+                        split_recorded = true;
+                    }
+                    ++pos[l];
+                    done[l] = 0;
+                }
+            }
+            if (!left) break;
+            if (!progress) return bfail(b, LBM_E_DEVICE, "batch: schedule stalled");   // not reached
+        }
+        if (straddle)
+            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(b->ev_lane[l], b->lane[l]);
+        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+        first_round = false;
         b->steps += k;
         for (auto *c : b->ctx) c->steps += k;
         n -= k;
     }
+    // join: the batch stream and the contexts' streams wait for both lanes
+    for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(b->ev_lane[l], b->lane[l]);
+    for (int l = 0; l < 2 && e == hipSuccess; ++l) {
+        e = hipStreamWaitEvent(b->stream, b->ev_lane[l], 0);
+        for (hipStream_t s : b->ctx_streams)
+            if (e == hipSuccess && s != b->stream) e = hipStreamWaitEvent(s, b->ev_lane[l], 0);
+    }
+    if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch join: ") + hipGetErrorString(e));
     return LBM_OK;
 }
 

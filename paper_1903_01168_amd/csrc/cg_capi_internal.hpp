@@ -54,21 +54,32 @@ int validate(const lbm_params *p, std::string &msg);
 Layout layout(const lbm_params *p);
 void fill_desc(const lbm_params *p, cgd::SlotDesc &d);
 int default_tx(int nx, int ny);
-int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req);
+// `paired`: the launch shares the chip with a second one (a batch's lanes).
+int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool paired = false);
 
 // Lattices stepped together whose buffers exceed the last-level cache are
 // split into contiguous groups that fit (MI355X: 256 MB Infinity Cache) and
 // the groups take turns: a group's populations then stay cache-resident from
 // one step to the next.  Lattices are independent, so results do not change.
 constexpr size_t kCacheBudget = 192ull << 20;
+// A batch steps two groups at a time on two streams (the second launch fills
+// the chip while the first one's last wavefronts finish), so its groups are
+// sized for two of them to fit the cache together.
+// Measured on nine 512^2 FP32 lattices (340 MB): groups of three with two in
+// flight (226 MB) +15-28% over groups of five and four taking turns; groups
+// of two or three and two (below the budget) and of five and four in flight
+// together (beyond the cache) were slower.
+constexpr size_t kPairBudget = 240ull << 20;
 // First index of each group (plus the end), balanced by bytes; `bytes` holds
-// the device bytes that each lattice's steps touch (its two buffers).
-std::vector<int> cache_groups(const std::vector<size_t> &bytes);
+// the device bytes that each lattice's steps touch (its two buffers).  At
+// least `min_groups` groups where there are that many lattices.
+std::vector<int> cache_groups(const std::vector<size_t> &bytes, size_t budget = kCacheBudget, int min_groups = 1);
 // The same within each run of consecutive lattices of one kind (kind[i]: the
 // step-kernel variant the lattice needs), so that every lattice is stepped by
 // the kernel variant it would get alone and its result does not depend on
 // its neighbours.
-std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind);
+std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind,
+                              size_t budget = kCacheBudget, int min_groups = 1);
 void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip);
 
 }  // namespace cgi

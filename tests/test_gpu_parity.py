@@ -425,3 +425,45 @@ def test_batch_cache_groups_bit_identical():
     finally:
         for lat in lats:
             lat.close()
+
+
+def test_batch_lanes_bit_identical():
+    """Groups of unequal size stepped two at a time on two streams, in calls
+    of uneven length (partial rounds; the group that straddles the two
+    streams' halves split between them), with the contexts' own streams used
+    right after each call (moments) and before the next (setting an inlet
+    colour is not needed: a population write instead): every lattice equals
+    itself stepped alone, bit for bit."""
+    cases = [W.bubble_cell(g, m, 40, n=n) for g, m, n in ((1, 1, 192), (10, 1, 256), (100, 10, 128), (5, 2, 320),
+                                                          (2, 20, 160))]
+    kicks = {1: 0.999}                       # after the second call, lattice 1's populations are scaled
+    calls = (1, 63, 300, 7, 256)
+    alone = []
+    for i, c in enumerate(cases):
+        with capi.Lattice(c["params"]) as g:
+            g.init(c["rho_r"], c["rho_b"])
+            for j, n in enumerate(calls):
+                g.step(n)
+                if j == 1 and i in kicks:
+                    g.set_pops(g.get_pops() * kicks[i])
+            alone.append(g.get_pops())
+    lats = [capi.Lattice(c["params"]) for c in cases]
+    for lat, c in zip(lats, cases):
+        lat.init(c["rho_r"], c["rho_b"])
+    try:
+        with capi.Batch(lats) as b:
+            assert b.groups >= 2
+            say(f"batch of {len(cases)} lattices in {b.groups} groups on two streams")
+            for j, n in enumerate(calls):
+                b.step(n)
+                m = [lat.moments() for lat in lats]      # on the contexts' streams
+                assert all(np.isfinite(x["rho_r"]).all() for x in m)
+                if j == 1:
+                    for i, f in kicks.items():
+                        lats[i].set_pops(lats[i].get_pops() * f)
+            for lat, ref in zip(lats, alone):
+                assert lat.steps_done == sum(calls)
+                assert np.array_equal(lat.get_pops(), ref)
+    finally:
+        for lat in lats:
+            lat.close()
