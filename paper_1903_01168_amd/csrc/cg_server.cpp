@@ -125,6 +125,10 @@ struct FakeBackend : Backend {
 struct GpuBackend : Backend {
     int storage, tx, device = 0, max_slots;
     hipStream_t stream = nullptr, cap = nullptr;
+    // two lanes (streams) step two cache groups of a chunk at a time; the
+    // server stream forks to them after the table upload and joins them
+    hipStream_t lane[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_lane[2] = {nullptr, nullptr};
     bool own_stream = false;
     cgd::SlotDesc *d_slots = nullptr;
     std::vector<cgd::SlotDesc> table;
@@ -141,10 +145,16 @@ struct GpuBackend : Backend {
     ~GpuBackend() override
     {
         if (stream) (void)hipStreamSynchronize(stream);
+        for (hipStream_t l : lane)
+            if (l) (void)hipStreamSynchronize(l);
         for (auto &c : chunks)
             if (c.graph) (void)hipGraphExecDestroy(c.graph);
         if (d_slots) (void)hipFree(d_slots);
         if (cap) (void)hipStreamDestroy(cap);
+        for (hipStream_t l : lane)
+            if (l) (void)hipStreamDestroy(l);
+        for (hipEvent_t ev : {ev_fork, ev_lane[0], ev_lane[1]})
+            if (ev) (void)hipEventDestroy(ev);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
     int setup(void *user_stream, std::string &err)
@@ -163,6 +173,14 @@ struct GpuBackend : Backend {
         if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipMalloc(&d_slots, (size_t)max_slots * sizeof(cgd::SlotDesc))) != hipSuccess) {
             d_slots = nullptr;
+            err = hipGetErrorString(e);
+            return LBM_E_DEVICE;
+        }
+        for (hipStream_t &l : lane)
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&l, hipStreamNonBlocking);
+        for (hipEvent_t *ev : {&ev_fork, &ev_lane[0], &ev_lane[1]})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
             err = hipGetErrorString(e);
             return LBM_E_DEVICE;
         }
@@ -190,8 +208,11 @@ struct GpuBackend : Backend {
         }
         return rc;
     }
-    // Chunk of K steps over the active lattices: cache-sized groups (in
-    // admission order) run their K launches in turn, each from its own graph.
+    // Chunk of K steps over the active lattices: groups (in admission order)
+    // sized so that two fit the cache together, each running its K launches
+    // from its own graph; with several groups, two lanes take whole groups
+    // (largest first, to the lane with less work queued), so that two
+    // groups are in flight at a time.
     int launch_chunk(const std::vector<Request *> &act, int K, std::string &err) override
     {
         (void)hipSetDevice(device);
@@ -202,19 +223,29 @@ struct GpuBackend : Backend {
             bytes.push_back(2 * r->ctx->buf_bytes);
             kind.push_back((char)cgd::step_variant(r->ctx->desc));
         }
-        const std::vector<int> first = cgi::cache_groups(bytes, kind);
+        const std::vector<int> first = cgi::cache_groups(bytes, kind, cgi::kPairBudget / 2, 2);
         const int ng = (int)first.size() - 1;
         std::vector<int> gtiles(ng, 0);
         std::vector<int> gvar(ng, 0);      // the group's step-kernel variant
+        std::vector<long long> gnodes(ng, 0);
+        for (int g = 0; g < ng; ++g)
+            for (int i = first[g]; i < first[g + 1]; ++i) gnodes[g] += act[i]->nodes();
+        // strips planned for what shares the chip: the two largest groups
+        long long pair_nodes = 0;
+        {
+            std::vector<long long> srt(gnodes);
+            std::sort(srt.begin(), srt.end());
+            pair_nodes = srt.back() + (ng > 1 ? srt[ng - 2] : 0);
+        }
         for (int g = 0; g < ng; ++g) {
-            long long tiles = 0, nodes = 0;
-            for (int i = first[g]; i < first[g + 1]; ++i) nodes += act[i]->nodes();
+            long long tiles = 0;
             for (int i = first[g]; i < first[g + 1]; ++i) {
                 const Request *r = act[i];
                 lbm_ctx *c = r->ctx;
                 cgd::SlotDesc d = c->desc;
                 cgi::set_geometry(d, &c->p, c->lay, tx, 1);
-                cgi::set_geometry(d, &c->p, c->lay, tx, cgi::plan_strip(nodes, c->p.ny, d.tiles_x, c->p.storage, 0));
+                cgi::set_geometry(d, &c->p, c->lay, tx,
+                                  cgi::plan_strip(pair_nodes, c->p.ny, d.tiles_x, c->p.storage, 0, ng > 1));
                 d.tile_begin = (int)tiles;
                 d.active_steps = (int)std::min<int64_t>(K, r->steps - r->done);
                 if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // launch 0 reads the current buffer
@@ -231,6 +262,21 @@ struct GpuBackend : Backend {
         hipError_t e = hipMemcpyAsync(d_slots, table.data(), table.size() * sizeof(cgd::SlotDesc),
                                       hipMemcpyHostToDevice, stream);
         if ((int)chunks.size() < ng) chunks.resize(ng);
+        // lane of each group: largest first, to the lane with less work
+        std::vector<int> glane(ng, -1), order(ng);
+        for (int g = 0; g < ng; ++g) order[g] = g;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gnodes[a] > gnodes[b]; });
+        long long load[2] = {0, 0};
+        for (int g : order) {
+            const int l = load[1] < load[0] ? 1 : 0;
+            glane[g] = l;
+            load[l] += gnodes[g];
+        }
+        if (ng > 1) {
+            if (e == hipSuccess) e = hipEventRecord(ev_fork, stream);
+            for (hipStream_t l : lane)
+                if (e == hipSuccess) e = hipStreamWaitEvent(l, ev_fork, 0);
+        }
         for (int g = 0; g < ng && e == hipSuccess; ++g) {
             Chunk &ch = chunks[g];
             const int off = first[g], ns = first[g + 1] - first[g], nt = gtiles[g];
@@ -250,7 +296,11 @@ struct GpuBackend : Backend {
                 if (e == hipSuccess) ch = Chunk{ch.graph, off, ns, nt, K, var};
                 else ch = Chunk{};
             }
-            if (e == hipSuccess) e = hipGraphLaunch(ch.graph, stream);
+            if (e == hipSuccess) e = hipGraphLaunch(ch.graph, ng > 1 ? lane[glane[g]] : stream);
+        }
+        if (ng > 1) {
+            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(ev_lane[l], lane[l]);
+            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipStreamWaitEvent(stream, ev_lane[l], 0);
         }
         if (e != hipSuccess) {
             err = hipGetErrorString(e);
