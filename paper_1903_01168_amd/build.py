@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcglbm.so")
 SOURCES = ["cg_kernels.hip", "cg_capi.cpp", "cg_server.cpp"]
-HEADERS = ["cg_device.hpp", "cg_kernels.hpp", "cg_capi_internal.hpp"]
+HEADERS = ["cg_device.hpp", "cg_kernels.hpp", "cg_capi_internal.hpp", "cg_schedule.hpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions (v_pk_*_f32) in device code.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

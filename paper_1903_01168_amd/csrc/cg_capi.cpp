@@ -15,6 +15,7 @@
 
 #include "cg_capi_internal.hpp"
 #include "cg_kernels.hpp"
+#include "cg_schedule.hpp"
 #include "cglbm.h"
 
 using cgd::SlotDesc;
@@ -965,61 +966,22 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
             if (e == hipSuccess) e = hipStreamWaitEvent(l, b->ev_join, 0);
     }
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch fork: ") + hipGetErrorString(e));
-    // Rounds of kRoundSteps steps per group.  In a round the groups' work
-    // (nodes x steps) is cut into two halves, one per lane, in the order of
-    // the groups, wrapping around (McNaughton's schedule): lane 0 takes the
-    // first groups, lane 1 the last ones, and the group that straddles the
-    // cut makes its first steps at the start of lane 1 and its last steps at
-    // the end of lane 0, after an event.  At most two groups are in flight at
-    // any time, and the lanes finish a round together.  Where a group
-    // straddles the cut, each lane's next round waits for the other lane's
-    // end (the group may sit differently in a shorter last round).
+    // Rounds of kRoundSteps steps per group, planned by cgs::plan_round (the
+    // group in which the half falls is split between the lanes, its two
+    // parts ordered by an event; where the half falls inside a group each
+    // lane's next round waits for the other lane's end).
+    std::vector<long long> gnodes;
+    for (auto &G : b->groups) gnodes.push_back(G.nodes);
     bool first_round = true;
     while (n > 0) {
         const int64_t k = std::min(n, kRoundSteps);
-        const int ng = (int)b->groups.size();
-        double total = 0;
-        for (auto &G : b->groups) total += (double)G.nodes;
-        const double half = 0.5 * total;
-        int cut = ng;                    // the first group not wholly on lane 0
-        int64_t s1 = 0;                  // its steps on lane 1 (its first s1 steps)
-        bool straddle = false;           // it has a share of lane 0 as well
-        double acc = 0;
-        for (int gi = 0; gi < ng; ++gi) {
-            const double w = (double)b->groups[gi].nodes;
-            if (acc + w <= half * (1 + 1e-9)) {
-                acc += w;
-                continue;
-            }
-            cut = gi;
-            // lane 0 keeps the last (half - acc) / w of its k steps, in whole
-            // graph replays when the round is long enough for them
-            const double f0 = (half - acc) / w;
-            straddle = f0 > 1e-9;
-            int64_t on0 = (int64_t)std::llround(f0 * (double)k);
-            if (k >= 2 * kGraphSteps) on0 = (on0 + kGraphSteps / 2) / kGraphSteps * kGraphSteps;
-            on0 = std::max<int64_t>(0, std::min<int64_t>(k, on0));
-            s1 = k - on0;
-            break;
-        }
-        const bool split = cut < ng && s1 > 0 && s1 < k;
+        const cgs::RoundPlan plan = cgs::plan_round(gnodes, k, kGraphSteps);
+        const bool split = plan.cut >= 0;
         const int64_t t0 = b->steps;
-        if (!first_round && straddle)
+        if (!first_round && plan.straddle)
             for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lane[l], b->ev_lane[1 - l], 0);
         if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
-        // the work of each lane: lane 1 the straddling group's first steps,
-        // then the groups after it; lane 0 the groups before the cut, then
-        // the straddling group's rest (after the event that ends its first
-        // steps)
-        struct Item {
-            int g;
-            int64_t start, steps;
-        };
-        std::vector<Item> work[2];
-        if (cut < ng && s1 > 0) work[1].push_back({cut, t0, s1});
-        for (int gi = cut + 1; gi < ng; ++gi) work[1].push_back({gi, t0, k});
-        for (int gi = 0; gi < std::min(cut, ng); ++gi) work[0].push_back({gi, t0, k});
-        if (cut < ng && s1 < k) work[0].push_back({cut, t0 + s1, k - s1});
+        const std::vector<cgs::LaneItem> *work = plan.lane;
         // queued in turns of one graph replay per lane, so that both lanes
         // have work from the start even when queueing is slower than the GPU
         size_t pos[2] = {0, 0};
@@ -1030,19 +992,19 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
             for (int l = 1; l >= 0; --l) {
                 if (pos[l] >= work[l].size()) continue;
                 left = true;
-                const Item &it = work[l][pos[l]];
-                const bool rest = split && l == 0 && it.g == cut;
+                const cgs::LaneItem &it = work[l][pos[l]];
+                const bool rest = split && l == 0 && it.group == plan.cut;
                 if (rest && !split_recorded) continue;            // its event is queued by lane 1 first
                 if (rest && done[l] == 0 && (e = hipStreamWaitEvent(b->lane[0], b->ev_split, 0)) != hipSuccess)
                     return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
                 const int64_t rem = it.steps - done[l];
                 const int64_t chunk = rem >= kGraphSteps ? kGraphSteps : rem;
-                const int rc = group_steps(b, b->groups[it.g], it.start + done[l], chunk, b->lane[l]);
+                const int rc = group_steps(b, b->groups[it.group], t0 + it.first + done[l], chunk, b->lane[l]);
                 if (rc != LBM_OK) return rc;
                 done[l] += chunk;
                 progress = true;
                 if (done[l] == it.steps) {
-                    if (split && l == 1 && it.g == cut) {
+                    if (split && l == 1 && it.group == plan.cut) {
                         if ((e = hipEventRecord(b->ev_split, b->lane[1])) != hipSuccess)
                             return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
                         split_recorded = true;
@@ -1054,7 +1016,7 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
             if (!left) break;
             if (!progress) return bfail(b, LBM_E_DEVICE, "batch: schedule stalled");   // not reached
         }
-        if (straddle)
+        if (plan.straddle)
             for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(b->ev_lane[l], b->lane[l]);
         if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
         first_round = false;

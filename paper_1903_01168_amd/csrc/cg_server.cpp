@@ -27,6 +27,7 @@
 
 #include "cg_capi_internal.hpp"
 #include "cg_kernels.hpp"
+#include "cg_schedule.hpp"
 #include "cglbm.h"
 #include "cglbm_serve.h"
 
@@ -262,16 +263,7 @@ struct GpuBackend : Backend {
         hipError_t e = hipMemcpyAsync(d_slots, table.data(), table.size() * sizeof(cgd::SlotDesc),
                                       hipMemcpyHostToDevice, stream);
         if ((int)chunks.size() < ng) chunks.resize(ng);
-        // lane of each group: largest first, to the lane with less work
-        std::vector<int> glane(ng, -1), order(ng);
-        for (int g = 0; g < ng; ++g) order[g] = g;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gnodes[a] > gnodes[b]; });
-        long long load[2] = {0, 0};
-        for (int g : order) {
-            const int l = load[1] < load[0] ? 1 : 0;
-            glane[g] = l;
-            load[l] += gnodes[g];
-        }
+        const std::vector<int> glane = cgs::assign_whole(gnodes);
         if (ng > 1) {
             if (e == hipSuccess) e = hipEventRecord(ev_fork, stream);
             for (hipStream_t l : lane)
