@@ -6,8 +6,10 @@
  * lbm_enqueue_solve from any thread.  A server thread admits them in arrival
  * order as slots and device memory free up (HBM budget), keeps their
  * populations resident, and advances ALL active lattices with one kernel
- * launch per time step (the batched step of cglbm.h), in chunks of
- * chunk_steps launches replayed from a captured HIP graph.  A request that
+ * launch per time step and group of lattices (the batched step of cglbm.h:
+ * groups sized so that two fit the Infinity Cache together, two of them in
+ * flight on two streams), in chunks of chunk_steps launches per group
+ * replayed from captured HIP graphs.  A request that
  * needs fewer steps than a chunk stops at its own count (the kernel leaves
  * its lattice alone for the remaining launches).  Finished lattices are
  * retired at chunk boundaries (FP64 diagnostics, optional fields copied to
