@@ -970,68 +970,75 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
     // group in which the half falls is split between the lanes, its two
     // parts ordered by an event; where the half falls inside a group each
     // lane's next round waits for the other lane's end).
-    std::vector<long long> gnodes;
-    for (auto &G : b->groups) gnodes.push_back(G.nodes);
-    bool first_round = true;
-    while (n > 0) {
-        const int64_t k = std::min(n, kRoundSteps);
-        const cgs::RoundPlan plan = cgs::plan_round(gnodes, k, kGraphSteps);
-        const bool split = plan.cut >= 0;
-        const int64_t t0 = b->steps;
-        if (!first_round && plan.straddle)
-            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lane[l], b->ev_lane[1 - l], 0);
-        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
-        const std::vector<cgs::LaneItem> *work = plan.lane;
-        // queued in turns of one graph replay per lane, so that both lanes
-        // have work from the start even when queueing is slower than the GPU
-        size_t pos[2] = {0, 0};
-        int64_t done[2] = {0, 0};
-        bool split_recorded = !split;
-        for (;;) {
-            bool progress = false, left = false;
-            for (int l = 1; l >= 0; --l) {
-                if (pos[l] >= work[l].size()) continue;
-                left = true;
-                const cgs::LaneItem &it = work[l][pos[l]];
-                const bool rest = split && l == 0 && it.group == plan.cut;
-                if (rest && !split_recorded) continue;            // its event is queued by lane 1 first
-                if (rest && done[l] == 0 && (e = hipStreamWaitEvent(b->lane[0], b->ev_split, 0)) != hipSuccess)
-                    return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
-                const int64_t rem = it.steps - done[l];
-                const int64_t chunk = rem >= kGraphSteps ? kGraphSteps : rem;
-                const int rc = group_steps(b, b->groups[it.group], t0 + it.first + done[l], chunk, b->lane[l]);
-                if (rc != LBM_OK) return rc;
-                done[l] += chunk;
-                progress = true;
-                if (done[l] == it.steps) {
-                    if (split && l == 1 && it.group == plan.cut) {
-                        if ((e = hipEventRecord(b->ev_split, b->lane[1])) != hipSuccess)
-                            return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
-                        split_recorded = true;
+    auto rounds = [&]() -> int {
+        std::vector<long long> gnodes;
+        for (auto &G : b->groups) gnodes.push_back(G.nodes);
+        bool first_round = true;
+        while (n > 0) {
+            const int64_t k = std::min(n, kRoundSteps);
+            const cgs::RoundPlan plan = cgs::plan_round(gnodes, k, kGraphSteps);
+            const bool split = plan.cut >= 0;
+            const int64_t t0 = b->steps;
+            if (!first_round && plan.straddle)
+                for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lane[l], b->ev_lane[1 - l], 0);
+            if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+            const std::vector<cgs::LaneItem> *work = plan.lane;
+            // queued in turns of one graph replay per lane, so that both lanes
+            // have work from the start even when queueing is slower than the GPU
+            size_t pos[2] = {0, 0};
+            int64_t done[2] = {0, 0};
+            bool split_recorded = !split;
+            for (;;) {
+                bool progress = false, left = false;
+                for (int l = 1; l >= 0; --l) {
+                    if (pos[l] >= work[l].size()) continue;
+                    left = true;
+                    const cgs::LaneItem &it = work[l][pos[l]];
+                    const bool rest = split && l == 0 && it.group == plan.cut;
+                    if (rest && !split_recorded) continue;            // its event is queued by lane 1 first
+                    if (rest && done[l] == 0 && (e = hipStreamWaitEvent(b->lane[0], b->ev_split, 0)) != hipSuccess)
+                        return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+                    const int64_t rem = it.steps - done[l];
+                    const int64_t chunk = rem >= kGraphSteps ? kGraphSteps : rem;
+                    const int rc = group_steps(b, b->groups[it.group], t0 + it.first + done[l], chunk, b->lane[l]);
+                    if (rc != LBM_OK) return rc;
+                    done[l] += chunk;
+                    progress = true;
+                    if (done[l] == it.steps) {
+                        if (split && l == 1 && it.group == plan.cut) {
+                            if ((e = hipEventRecord(b->ev_split, b->lane[1])) != hipSuccess)
+                                return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+                            split_recorded = true;
+                        }
+                        ++pos[l];
+                        done[l] = 0;
                     }
-                    ++pos[l];
-                    done[l] = 0;
                 }
+                if (!left) break;
+                if (!progress) return bfail(b, LBM_E_DEVICE, "batch: schedule stalled");   // not reached
             }
-            if (!left) break;
-            if (!progress) return bfail(b, LBM_E_DEVICE, "batch: schedule stalled");   // not reached
+            if (plan.straddle)
+                for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(b->ev_lane[l], b->lane[l]);
+            if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
+            first_round = false;
+            b->steps += k;
+            for (auto *c : b->ctx) c->steps += k;
+            n -= k;
         }
-        if (plan.straddle)
-            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(b->ev_lane[l], b->lane[l]);
-        if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch: ") + hipGetErrorString(e));
-        first_round = false;
-        b->steps += k;
-        for (auto *c : b->ctx) c->steps += k;
-        n -= k;
-    }
-    // join: the batch stream and the contexts' streams wait for both lanes
-    for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(b->ev_lane[l], b->lane[l]);
-    for (int l = 0; l < 2 && e == hipSuccess; ++l) {
-        e = hipStreamWaitEvent(b->stream, b->ev_lane[l], 0);
+        return LBM_OK;
+    };
+    const int rounds_rc = rounds();
+    // join (also after a failure): the batch stream and the contexts'
+    // streams wait for both lanes
+    hipError_t je = hipSuccess;
+    for (int l = 0; l < 2 && je == hipSuccess; ++l) je = hipEventRecord(b->ev_lane[l], b->lane[l]);
+    for (int l = 0; l < 2 && je == hipSuccess; ++l) {
+        je = hipStreamWaitEvent(b->stream, b->ev_lane[l], 0);
         for (hipStream_t s : b->ctx_streams)
-            if (e == hipSuccess && s != b->stream) e = hipStreamWaitEvent(s, b->ev_lane[l], 0);
+            if (je == hipSuccess && s != b->stream) je = hipStreamWaitEvent(s, b->ev_lane[l], 0);
     }
-    if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch join: ") + hipGetErrorString(e));
+    if (rounds_rc != LBM_OK) return rounds_rc;
+    if (je != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch join: ") + hipGetErrorString(je));
     return LBM_OK;
 }
 

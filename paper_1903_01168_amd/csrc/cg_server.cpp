@@ -290,9 +290,11 @@ struct GpuBackend : Backend {
             }
             if (e == hipSuccess) e = hipGraphLaunch(ch.graph, ng > 1 ? lane[glane[g]] : stream);
         }
-        if (ng > 1) {
-            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipEventRecord(ev_lane[l], lane[l]);
-            for (int l = 0; l < 2 && e == hipSuccess; ++l) e = hipStreamWaitEvent(stream, ev_lane[l], 0);
+        if (ng > 1) {   // join (also after a failure): the server stream waits for both lanes
+            hipError_t je = hipSuccess;
+            for (int l = 0; l < 2 && je == hipSuccess; ++l) je = hipEventRecord(ev_lane[l], lane[l]);
+            for (int l = 0; l < 2 && je == hipSuccess; ++l) je = hipStreamWaitEvent(stream, ev_lane[l], 0);
+            if (e == hipSuccess) e = je;
         }
         if (e != hipSuccess) {
             err = hipGetErrorString(e);
