@@ -1,6 +1,7 @@
 """Parity at the full sizes of the benchmark configurations, in the launch
-configuration bench.py times (one batched k_step launch per step, automatic
-tile width and strip height, HIP-graph replay): the nine 512 x 512 lattices of
+configuration bench.py times (a batch: one k_step launch per group of lattices
+and step, two groups in flight on two streams, automatic tile width and strip
+height, HIP-graph replay): the nine 512 x 512 lattices of
 the bubble sweep, the 4096 x 256 gravity slug and the 8192 x 512 inlet/outlet
 channel, each against the FP64 oracle after STEPS steps (one graph replay of
 32 steps plus single launches).
