@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
+VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4   # 614.4 G wave64 VALU instructions/s
 # the kernels and the host planner that picks their launch shape
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_01168_amd", "csrc", f)
                   for f in ("cg_device.hpp", "cg_kernels.hip", "cg_capi.cpp")]
@@ -466,16 +468,36 @@ def main():
     # when there are several, so the step's time is the union of the kernels'
     # busy intervals
     achieved = bpu * nodes / (ms_per_step / 1e3) / 1e9
-    traffic = None
+    # HBM bytes per launch and VALU instructions per lattice update, from the
+    # rocprofv3 counter runs summarised under profiles/ (only while the kernel
+    # sources are the ones those runs measured)
+    traffic, valu = None, None
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
             key = (f"{args.workload}/{args.storage}/{args.collision}" + ("/nsc" if args.ns_correction else "")
                    + ("/iso" if args.gradient == "isotropic" else ""))
-            if tr.get("kernel_hash") == kernel_hash() and key in tr.get("per_launch", {}):
-                traffic = tr["per_launch"][key]
+            if tr.get("kernel_hash") == kernel_hash():
+                traffic = tr.get("per_launch", {}).get(key)
+                valu = tr.get("valu_per_update", {}).get(key)
         except (OSError, ValueError):
-            traffic = None
+            traffic, valu = None, None
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "bytes_per_update": bpu, "kernel": "k_step", "launches_per_step": launches,
+                "kernel_hash": kernel_hash()}
+    if valu is not None:
+        # VALU issue: one wave64 instruction per SIMD every 4 cycles, 1024 SIMDs
+        # at 2.4 GHz (unpacked); the 16-bit codec makes those kernels VALU-bound
+        v = dict(per_update=valu, achieved=mlups * 1e6 * valu / 1e9, peak=VALU_PEAK_GIPS,
+                 unit="G wave64 VALU instructions/s")
+        v["frac"] = v["achieved"] / VALU_PEAK_GIPS
+        if args.storage == "f32":
+            roofline["valu"] = v
+        else:
+            hbm = {k: roofline[k] for k in ("achieved", "peak", "unit", "frac")}
+            roofline.update(bound="alu", achieved=v["achieved"], peak=v["peak"], unit=v["unit"], frac=v["frac"],
+                            valu_per_update=valu, hbm=hbm)
 
     cells_out = []
     for lat, c, m0 in zip(lats, cells, mass0):
@@ -515,10 +537,7 @@ def main():
                               "two fit the Infinity Cache together, two groups in flight on two streams (rounds "
                               "of 256 steps per group), HIP-graph replay of 32 steps" if launches > 1 else
                               "batched k_step, one launch per step, HIP-graph replay of 32 steps")},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_update": bpu, "kernel": "k_step", "launches_per_step": launches,
-                     "kernel_hash": kernel_hash()},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "precision": precision,
         "wall_s": wall,
