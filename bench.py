@@ -485,7 +485,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "bytes_per_update": bpu, "kernel": "k_step", "launches_per_step": launches,
-                "kernel_hash": kernel_hash()}
+                "step_us": ms_per_step * 1e3, "kernel_hash": kernel_hash()}
+    if launches > 1:
+        roofline["note"] = ("two k_step launches in flight on two streams: achieved = algorithmic bytes of a step / "
+                            "step time (HIP events on the batch stream), i.e. over the union of the launches' "
+                            "busy intervals, not per launch")
     if valu is not None:
         # VALU issue: one wave64 instruction per SIMD every 4 cycles, 1024 SIMDs
         # at 2.4 GHz (unpacked); the 16-bit codec makes those kernels VALU-bound
