@@ -31,7 +31,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4   # 614.4 G wave64 VALU instructions/s
 # the kernels and the host planner that picks their launch shape
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_01168_amd", "csrc", f)
-                  for f in ("cg_device.hpp", "cg_kernels.hip", "cg_capi.cpp")]
+                  for f in ("cg_device.hpp", "cg_kernels.hip", "cg_capi.cpp", "cg_schedule.hpp")]
 
 
 def kernel_hash():

@@ -241,42 +241,6 @@ int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool 
     return ny < s ? ny : s;
 }
 
-std::vector<int> cache_groups(const std::vector<size_t> &bytes, size_t budget, int min_groups)
-{
-    const int n = (int)bytes.size();
-    size_t total = 0;
-    for (size_t b : bytes) total += b;
-    const size_t want = std::max<size_t>((size_t)std::max(min_groups, 1), (total + budget - 1) / budget);
-    const int ng = (int)std::min<size_t>((size_t)std::max(n, 1), want);
-    std::vector<int> first(1, 0);
-    size_t acc = 0;
-    for (int i = 0, g = 1; i + 1 < n && g < ng; ++i) {
-        acc += bytes[i];
-        if (acc * ng >= total * g) {   // the groups so far hold their share
-            first.push_back(i + 1);
-            ++g;
-        }
-    }
-    first.push_back(n);
-    return first;
-}
-
-std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind, size_t budget,
-                              int min_groups)
-{
-    std::vector<int> first(1, 0);
-    const int n = (int)bytes.size();
-    for (int a = 0; a < n;) {
-        int e = a + 1;
-        while (e < n && kind[e] == kind[a]) ++e;
-        const std::vector<int> f =
-            cache_groups(std::vector<size_t>(bytes.begin() + a, bytes.begin() + e), budget, min_groups);
-        for (size_t j = 1; j < f.size(); ++j) first.push_back(a + f[j]);
-        a = e;
-    }
-    if (n == 0) first.push_back(0);
-    return first;
-}
 
 void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip)
 {

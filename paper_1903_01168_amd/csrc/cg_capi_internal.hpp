@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "cg_device.hpp"
+#include "cg_schedule.hpp"
 #include "cglbm.h"
 
 namespace cgi {
@@ -70,16 +71,13 @@ constexpr size_t kCacheBudget = 192ull << 20;
 // of two or three and two (below the budget) and of five and four in flight
 // together (beyond the cache) were slower.
 constexpr size_t kPairBudget = 240ull << 20;
-// First index of each group (plus the end), balanced by bytes; `bytes` holds
-// the device bytes that each lattice's steps touch (its two buffers).  At
-// least `min_groups` groups where there are that many lattices.
-std::vector<int> cache_groups(const std::vector<size_t> &bytes, size_t budget = kCacheBudget, int min_groups = 1);
-// The same within each run of consecutive lattices of one kind (kind[i]: the
-// step-kernel variant the lattice needs), so that every lattice is stepped by
-// the kernel variant it would get alone and its result does not depend on
-// its neighbours.
-std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind,
-                              size_t budget = kCacheBudget, int min_groups = 1);
+// The grouping itself (contiguous groups balanced by bytes, at least
+// `min_groups`, never mixing kinds) is cgs::cache_groups of cg_schedule.hpp.
+inline std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind,
+                                     size_t budget = kCacheBudget, int min_groups = 1)
+{
+    return cgs::cache_groups(bytes, kind, budget, min_groups);
+}
 void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip);
 
 }  // namespace cgi

@@ -1,5 +1,6 @@
-// cg_schedule.hpp -- how two lanes (streams) share the groups of lattices
-// that are stepped together.  Host-only planning with no HIP dependency.
+// cg_schedule.hpp -- how lattices stepped together are cut into groups that
+// stay in the last-level cache, and how two lanes (streams) share the
+// groups.  Host-only planning with no HIP dependency.
 //
 // A launch's wavefronts all start together but finish over a spread of
 // times; a second launch in flight on another stream fills the slots the
@@ -9,10 +10,58 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
 namespace cgs {
+
+// Lattices stepped together, in order, split into contiguous groups: as many
+// as the total of `bytes` (the device bytes each lattice's steps touch)
+// needs at `budget` per group, at least `min_groups`, at most one per
+// lattice; a group closes once the groups so far hold their share of the
+// total, or when the lattices left are just enough for one group each.
+// Returns the first index of each group, then the end.
+inline std::vector<int> cache_groups(const std::vector<size_t> &bytes, size_t budget, int min_groups)
+{
+    const int n = (int)bytes.size();
+    size_t total = 0;
+    for (size_t b : bytes) total += b;
+    const size_t want = std::max<size_t>((size_t)std::max(min_groups, 1), (total + budget - 1) / budget);
+    const int ng = (int)std::min<size_t>((size_t)std::max(n, 1), want);
+    std::vector<int> first(1, 0);
+    size_t acc = 0;
+    for (int i = 0, g = 1; i + 1 < n && g < ng; ++i) {
+        acc += bytes[i];
+        if (acc * ng >= total * g || n - (i + 1) == ng - g) {
+            first.push_back(i + 1);
+            ++g;
+        }
+    }
+    first.push_back(n);
+    return first;
+}
+
+// The same within each run of consecutive lattices of one kind (kind[i]: the
+// step-kernel variant the lattice needs), so that every lattice is stepped by
+// the kernel variant it would get alone and its result does not depend on
+// its neighbours.
+inline std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std::vector<char> &kind, size_t budget,
+                                     int min_groups)
+{
+    std::vector<int> first(1, 0);
+    const int n = (int)bytes.size();
+    for (int a = 0; a < n;) {
+        int e = a + 1;
+        while (e < n && kind[e] == kind[a]) ++e;
+        const std::vector<int> f =
+            cache_groups(std::vector<size_t>(bytes.begin() + a, bytes.begin() + e), budget, min_groups);
+        for (size_t j = 1; j < f.size(); ++j) first.push_back(a + f[j]);
+        a = e;
+    }
+    if (n == 0) first.push_back(0);
+    return first;
+}
 
 // `steps` consecutive steps of group `group`, starting `first` steps into
 // the round.

@@ -1,5 +1,5 @@
-"""The two-lane schedule of grouped lattices (host logic, no GPU): the
-planner header is compiled with g++ into a checker that plans rounds for
+"""The grouping of lattices and the two-lane schedule (host logic, no GPU):
+the planner header is compiled with g++ into a checker that plans rounds for
 many random group sizes and round lengths and checks the schedule's
 invariants.
 
@@ -14,6 +14,10 @@ invariants.
   the split group.
 - Whole-group assignment (the server's chunks): every group on a lane, and
   the larger lane holds at most half the work plus the largest group.
+- Cache groups: contiguous and non-empty, never across a change of kernel
+  variant, as many per run of one variant as its bytes need at the budget
+  (at least the minimum, at most one per lattice), each within its share of
+  the run plus one lattice.
 """
 import os
 import shutil
@@ -104,6 +108,45 @@ int main()
             mx = std::max(mx, (double)w[g]);
         }
         if (std::max(L[0], L[1]) > 0.5 * tot + mx + 1e-9) return fail("whole: out of balance", cases);
+    }
+    // cache groups: contiguous, non-empty, never across a change of kind, as
+    // many per run of one kind as its bytes need (at least min_groups, at
+    // most one per lattice), each within its share plus one lattice
+    for (int rep = 0; rep < 20000; ++rep) {
+        ++cases;
+        const int n = 1 + (int)(rng() % 12);
+        std::vector<size_t> bytes(n);
+        std::vector<char> kind(n);
+        for (int i = 0; i < n; ++i) {
+            bytes[i] = (size_t)(1 + rng() % 400) << 20;
+            kind[i] = (char)(rep % 4 == 0 ? 0 : rng() % 3);
+        }
+        const size_t budget = (size_t)(32 + rng() % 300) << 20;
+        const int ming = 1 + (int)(rng() % 3);
+        const std::vector<int> f = cgs::cache_groups(bytes, kind, budget, ming);
+        if (f.front() != 0 || f.back() != n) return fail("groups: ends", cases);
+        for (size_t j = 0; j + 1 < f.size(); ++j) {
+            if (f[j + 1] <= f[j]) return fail("groups: empty or unordered", cases);
+            for (int i = f[j] + 1; i < f[j + 1]; ++i)
+                if (kind[i] != kind[f[j]]) return fail("groups: mixed kinds", cases);
+        }
+        for (int a = 0; a < n;) {
+            int e = a + 1;
+            while (e < n && kind[e] == kind[a]) ++e;
+            size_t tot = 0, mx = 0;
+            for (int i = a; i < e; ++i) { tot += bytes[i]; mx = std::max(mx, bytes[i]); }
+            const long long want = std::min<long long>(e - a, std::max<long long>(ming, (long long)((tot + budget - 1) / budget)));
+            long long got = 0;
+            for (size_t j = 0; j + 1 < f.size(); ++j) {
+                if (f[j] < a || f[j] >= e) continue;
+                ++got;
+                size_t gb = 0;
+                for (int i = f[j]; i < f[j + 1]; ++i) gb += bytes[i];
+                if ((double)gb > (double)tot / (double)want + (double)mx + 1.0) return fail("groups: over share", cases);
+            }
+            if (got != want) return fail("groups: count", cases);
+            a = e;
+        }
     }
     std::printf("ok %d cases\n", cases);
     return 0;
