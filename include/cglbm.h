@@ -189,9 +189,20 @@ int lbm_set_pops(lbm_ctx *ctx, const double *host);
 int lbm_save_state(lbm_ctx *ctx, void *host, size_t cap, size_t *written);
 int lbm_load_state(lbm_ctx *ctx, const void *host, size_t n);
 
-/* Launch-shape control (tuning): columns per workgroup (64, 128 or 256) and
- * rows per workgroup strip (0 = automatic). */
+/* Launch-shape control (tuning): threads per workgroup (64, 128, 256, 512 or
+ * 1024: one to sixteen wavefronts side by side; 0 = planned) and rows per
+ * workgroup strip (0 = planned).  Results do not depend on either. */
 int lbm_set_launch(lbm_ctx *ctx, int32_t tile_x, int32_t strip_rows);
+/* Step-kernel flavour (tuning; nearest-neighbour gradient only -- the
+ * second-neighbour gradient always uses halo lanes): 1 = block exchange (each
+ * wavefront writes a whole 64-column block, edge columns exchanged through
+ * LDS and the workgroup's outer halo nodes gathered beside each row: whole
+ * cache lines written, for lattices beyond the last-level cache), 0 = halo
+ * lanes (each wavefront writes 60 columns and its outer lanes hold the
+ * neighbour columns), -1 = planned (block exchange for FP32 storage when both
+ * population buffers exceed 256 MiB).  Results do not depend on it.
+ * Errors: LBM_E_INVAL for another mode. */
+int lbm_set_exchange(lbm_ctx *ctx, int32_t mode);
 /* The HIP stream of the context (a hipStream_t). */
 void *lbm_stream(const lbm_ctx *ctx);
 

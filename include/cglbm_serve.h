@@ -78,8 +78,9 @@ typedef struct {
 /* hbm_budget: device bytes the active lattices may hold in total (their
  * lbm_bytes_required); max_slots: lattices advanced together (<= 4096);
  * chunk_steps: launches per chunk (even, >= 2); storage: LBM_STORE_* used for
- * every request (a request's own storage field is ignored); tile_x: 0, 64,
- * 128 or 256; hip_stream: NULL for a server-owned stream. */
+ * every request (a request's own storage field is ignored); tile_x: threads
+ * per workgroup, 64, 128 or 256, or 0 for the launch planner's choice per
+ * group of lattices; hip_stream: NULL for a server-owned stream. */
 int lbm_server_create(size_t hbm_budget, int32_t max_slots, int32_t chunk_steps, int32_t storage,
                       int32_t tile_x, void *hip_stream, lbm_server **out);
 /* The same scheduler with a host-only backend that performs no GPU work:

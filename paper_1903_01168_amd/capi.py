@@ -62,7 +62,7 @@ EXPORTS = [
     "lbm_version", "lbm_last_error", "lbm_bytes_required", "lbm_buffer_bytes", "lbm_create",
     "lbm_create_ext", "lbm_destroy", "lbm_init_fields", "lbm_set_inlet_color", "lbm_step",
     "lbm_steps_done", "lbm_sync", "lbm_moments", "lbm_diag", "lbm_get_pops", "lbm_set_pops",
-    "lbm_save_state", "lbm_load_state", "lbm_set_launch", "lbm_stream", "lbm_bw_copy",
+    "lbm_save_state", "lbm_load_state", "lbm_set_launch", "lbm_set_exchange", "lbm_stream", "lbm_bw_copy",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_groups",
 ]
 
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.lbm_save_state.argtypes = [_P, _P, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbm_load_state.argtypes = [_P, _P, C.c_size_t]
     L.lbm_set_launch.argtypes = [_P, C.c_int32, C.c_int32]
+    L.lbm_set_exchange.argtypes = [_P, C.c_int32]
     L.lbm_stream.restype = _P
     L.lbm_stream.argtypes = [_P]
     L.lbm_bw_copy.argtypes = [_P, _P, _P, C.c_size_t]
@@ -259,8 +260,11 @@ class Lattice:
     def load_state(self, blob: bytes):
         self._check(self.L.lbm_load_state(self._h, blob, len(blob)))
 
-    def set_launch(self, tile_x=0, strip_rows=0):
+    def set_launch(self, tile_x=0, strip_rows=0, exchange=None):
+        """Threads per workgroup and rows per strip (0: planned); exchange:
+        True / False forces the block-exchange / halo-lane step, None plans."""
         self._check(self.L.lbm_set_launch(self._h, int(tile_x), int(strip_rows)))
+        self._check(self.L.lbm_set_exchange(self._h, -1 if exchange is None else int(bool(exchange))))
 
     def bw_copy(self, dst_ptr, src_ptr, nbytes):
         self._check(self.L.lbm_bw_copy(self._h, _P(dst_ptr), _P(src_ptr), int(nbytes)))

@@ -202,20 +202,54 @@ void fill_desc(const lbm_params *p, SlotDesc &d)
     d.wet_s = end ? 0.f : (float)std::sin(rad);
 }
 
-// One wavefront per workgroup suits lattices up to a few million nodes (finer
-// load balance); four wavefronts side by side stream longer row segments,
-// which pays from about 4M nodes (8192 x 512 channel: +3% in FP32).
+// Halo lanes: one wavefront per workgroup suits lattices up to a few million
+// nodes (finer load balance); four wavefronts side by side stream longer row
+// segments, which pays from about 4M nodes.
 int default_tx(int nx, int ny) { return (long long)nx * ny >= (1LL << 22) ? 256 : 64; }
 
-static int wave_tiles(int nx, bool iso)
+// The exchange flavour (whole 64-column blocks per wavefront, edge columns
+// through LDS) for FP32 launches whose populations (both buffers of every
+// lattice) exceed the 256 MB Infinity Cache: there each row of a plane must
+// be written in whole cache lines, and the halo-lane flavour's stores, which
+// split lines between wavefronts, cost a read-modify-write in DRAM.  Inside
+// the cache the halo lanes are faster (no barrier, no halo gather on the row's
+// critical path), and so they are for 16-bit storage, whose step is bound by
+// its codec's arithmetic.  Measured on MI355X: 8192 x 512 channel 31.0k
+// against 27.4k MLUPS, 8192^2 bubble 35.0k against 27.7k; 4096 x 256 slug
+// (151 MB) 29.7k against 35.8k, 1024^2 bubble 30.3k against 36.7k.
+bool plan_exchange(size_t bytes, int storage, int variant)
 {
-    const int cols = cgd::wave_cols(iso);
+    return storage == LBM_STORE_F32 && !(variant & cgd::KV_ISO) && bytes > kXchBytes;
+}
+
+// Exchange flavour: the widest workgroup (up to 16 wavefronts, 1024 columns)
+// that still leaves several workgroups across the lattice; at most 8 with the
+// Navier-Stokes correction, whose step needs more than the 128 VGPRs per lane
+// that 16 wavefronts on a CU leave (a 1024-thread workgroup would spill).
+int xch_tx(int nx, int variant)
+{
+    const int blocks = (nx + 63) / 64;
+    const int tx = blocks >= 32 ? 1024 : (blocks >= 16 ? 512 : (blocks >= 8 ? 256 : 64));
+    return (variant & cgd::KV_NSC) ? std::min(tx, 512) : tx;
+}
+
+static int wave_tiles(int nx, bool iso, bool xch)
+{
+    const int cols = cgd::wave_cols(iso, xch);
     return (nx + cols - 1) / cols;
 }
 
-int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool paired)
+int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool paired, bool xch)
 {
     if (req > 0) return req < ny ? req : ny;
+    if (xch) {
+        // the tallest strip (fewest halo rows, each gathered twice) that
+        // still gives every CU a workgroup: 8192 x 512 channel 16 rows
+        // (31.0k MLUPS against 29.6k with 8)
+        int s = 16;
+        while (s > 1 && (long long)tiles_x * ((ny + s - 1) / s) < 256) s /= 2;
+        return ny < s ? ny : s;
+    }
     // A wavefront marches through its strip row by row, each row a dependent
     // load -> collide -> store round trip (~1.5-2.5 us), so a launch takes at
     // least strip x that.  Few nodes in the launch: short strips (latency);
@@ -242,16 +276,34 @@ int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool 
 }
 
 
-void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip)
+void set_geometry(SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip, bool xch)
 {
     d.nx = p->nx;
     d.ny = p->ny;
     d.pitch = L.pitch;
     d.plane = L.plane;
+    d.row_bytes = (uint32_t)((L.pitch / 64) * (p->storage == LBM_STORE_F32 ? cgd::blk_bytes<cgd::ST_F32>()
+                                                                      : cgd::blk_bytes<cgd::ST_F16S>()));
     d.strip = strip;
     const int waves = tx / 64;
-    d.tiles_x = (wave_tiles(p->nx, p->gradient == 1) + waves - 1) / waves;   // workgroups across x
+    d.tiles_x = (wave_tiles(p->nx, p->gradient == 1, xch) + waves - 1) / waves;   // workgroups across x
     d.tiles_y = (p->ny + strip - 1) / strip;
+}
+
+GroupPlan plan_group(size_t bytes, int storage, int variant, int req_tx, lbm_ctx *const *ctxs, int n)
+{
+    GroupPlan g;
+    const bool xch = plan_exchange(bytes, storage, variant);
+    g.variant = variant | (xch ? cgd::KV_XCH : 0);
+    if (req_tx) {
+        g.tx = req_tx;
+    } else {
+        // the widest workgroup every lattice of the group fills
+        g.tx = xch ? 1024 : 256;
+        for (int i = 0; i < n; ++i)
+            g.tx = std::min(g.tx, xch ? xch_tx(ctxs[i]->p.nx, variant) : default_tx(ctxs[i]->p.nx, ctxs[i]->p.ny));
+    }
+    return g;
 }
 
 }  // namespace cgi
@@ -276,10 +328,14 @@ static void drop_graphs(lbm_ctx *c)
 
 static int replan(lbm_ctx *c)
 {
-    const int tx = c->tx ? c->tx : default_tx(c->p.nx, c->p.ny);
-    set_geometry(c->desc, &c->p, c->lay, tx, 1);   // tiles_x does not depend on the strip
-    const int strip = plan_strip((long long)c->p.nx * c->p.ny, c->p.ny, c->desc.tiles_x, c->p.storage, c->strip_req);
-    set_geometry(c->desc, &c->p, c->lay, tx, strip);
+    const int var = cgd::step_variant(c->desc);
+    c->xch = c->xch_req >= 0 ? (c->xch_req == 1 && !(var & cgd::KV_ISO))
+                             : plan_exchange(2 * c->buf_bytes, c->p.storage, var);
+    const int tx = c->tx_req ? c->tx_req : (c->xch ? xch_tx(c->p.nx, var) : default_tx(c->p.nx, c->p.ny));
+    set_geometry(c->desc, &c->p, c->lay, tx, 1, c->xch);   // tiles_x does not depend on the strip
+    const int strip = plan_strip((long long)c->p.nx * c->p.ny, c->p.ny, c->desc.tiles_x, c->p.storage, c->strip_req,
+                                 false, c->xch);
+    set_geometry(c->desc, &c->p, c->lay, tx, strip, c->xch);
     c->desc.tile_begin = 0;
     c->desc.active_steps = INT_MAX;
     c->tiles = c->desc.tiles_x * c->desc.tiles_y;
@@ -413,12 +469,21 @@ int lbm_destroy(lbm_ctx *c)
 int lbm_set_launch(lbm_ctx *c, int32_t tile_x, int32_t strip_rows)
 {
     if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
-    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256)
-        return fail(c, LBM_E_INVAL, "tile_x must be 0, 64, 128 or 256");
+    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512 && tile_x != 1024)
+        return fail(c, LBM_E_INVAL, "tile_x must be 0, 64, 128, 256, 512 or 1024");
     if (strip_rows < 0) return fail(c, LBM_E_INVAL, "strip_rows must be >= 0");
     DeviceGuard g(c->device);
-    c->tx = tile_x;
+    c->tx_req = tile_x;
     c->strip_req = strip_rows;
+    return replan(c);
+}
+
+int lbm_set_exchange(lbm_ctx *c, int32_t mode)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (mode < -1 || mode > 1) return fail(c, LBM_E_INVAL, "mode must be -1 (planned), 0 or 1");
+    DeviceGuard g(c->device);
+    c->xch_req = mode;
     return replan(c);
 }
 
@@ -464,6 +529,8 @@ int lbm_set_inlet_color(lbm_ctx *c, const int8_t *color_y)
 
 static const int kGraphSteps = 32;   // steps per captured graph (even)
 
+static int ctx_variant(const lbm_ctx *c) { return cgd::step_variant(c->desc) | (c->xch ? cgd::KV_XCH : 0); }
+
 static int build_graph(lbm_ctx *c, int parity)
 {
     hipGraph_t graph = nullptr;
@@ -472,7 +539,7 @@ static int build_graph(lbm_ctx *c, int parity)
     hipError_t le = hipSuccess;
     for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
         le = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (parity + j) & 1, 0, c->cap_stream,
-                              cgd::step_variant(c->desc));
+                              ctx_variant(c));
     e = hipStreamEndCapture(c->cap_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -505,7 +572,7 @@ int lbm_step(lbm_ctx *c, int64_t n)
     }
     for (; n > 0; --n) {
         hipError_t e = cgd::launch_step(c->p.storage, c->tx, c->d_desc, 1, c->tiles, (int)(c->steps & 1), 0, c->stream,
-                                        cgd::step_variant(c->desc));
+                                        ctx_variant(c));
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->steps++;
     }
@@ -634,7 +701,7 @@ int lbm_save_state(lbm_ctx *c, void *host, size_t cap, size_t *written)
     DeviceGuard g(c->device);
     StateHeader h{};
     std::memcpy(h.magic, "CGLBMST1", 8);
-    h.version = 1;
+    h.version = 2;   // 2: populations in blocks of 64 columns
     h.nx = c->p.nx;
     h.ny = c->p.ny;
     h.storage = c->p.storage;
@@ -654,7 +721,8 @@ int lbm_load_state(lbm_ctx *c, const void *host, size_t n)
     StateHeader h;
     if (n < sizeof h) return fail(c, LBM_E_INVAL, "state too short");
     std::memcpy(&h, host, sizeof h);
-    if (std::memcmp(h.magic, "CGLBMST1", 8) != 0 || h.version != 1) return fail(c, LBM_E_INVAL, "not a state blob");
+    if (std::memcmp(h.magic, "CGLBMST1", 8) != 0 || h.version != 2)
+        return fail(c, LBM_E_INVAL, "not a state blob of this layout (version 2)");
     if (h.nx != c->p.nx || h.ny != c->p.ny || h.storage != c->p.storage || h.pitch != c->lay.pitch ||
         h.bytes != c->buf_bytes || n < sizeof h + c->buf_bytes)
         return fail(c, LBM_E_INVAL, "state does not match this lattice");
@@ -686,7 +754,8 @@ struct BatchGroup {
     SlotDesc *d_slots = nullptr;
     int tiles = 0;
     long long nodes = 0;
-    int variant = 0;                    // step-kernel variant of its lattices (one per group)
+    int variant = 0;                    // step-kernel variant of its launches (one per group, KV_XCH included)
+    int tx = 0;                         // threads per workgroup
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
@@ -701,7 +770,7 @@ struct lbm_batch {
     hipStream_t lane[2] = {nullptr, nullptr};
     hipEvent_t ev_join = nullptr, ev_split = nullptr, ev_lane[2] = {nullptr, nullptr};
     std::vector<hipStream_t> ctx_streams;   // distinct streams of the contexts
-    int device = 0, storage = 0, tx = 0;
+    int device = 0, storage = 0;
     int64_t steps = 0;
     std::string err;
 };
@@ -741,8 +810,8 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
 {
     if (!out || !ctxs || n < 1) return fail(nullptr, LBM_E_INVAL, "batch: need at least one context");
     *out = nullptr;
-    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256)
-        return fail(nullptr, LBM_E_INVAL, "tile_x must be 0, 64, 128 or 256");
+    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512 && tile_x != 1024)
+        return fail(nullptr, LBM_E_INVAL, "tile_x must be 0, 64, 128, 256, 512 or 1024");
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return fail(nullptr, LBM_E_INVAL, "batch: NULL context");
         if (ctxs[i]->device != ctxs[0]->device || ctxs[i]->p.storage != ctxs[0]->p.storage)
@@ -755,12 +824,6 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
     b->device = ctxs[0]->device;
     b->storage = ctxs[0]->p.storage;
     DeviceGuard g(b->device);
-    int tx = tile_x;
-    if (!tx) {
-        tx = 256;
-        for (int i = 0; i < n; ++i) tx = std::min(tx, default_tx(ctxs[i]->p.nx, ctxs[i]->p.ny));
-    }
-    b->tx = tx;
     std::vector<size_t> bytes;
     std::vector<char> kind;
     for (int i = 0; i < n; ++i) {
@@ -786,20 +849,31 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_
     for (int gi = 0; gi < ngroups; ++gi) {
         BatchGroup &G = b->groups[gi];
         long long tiles = 0, nodes = 0;
-        for (int i = first[gi]; i < first[gi + 1]; ++i) nodes += (long long)ctxs[i]->p.nx * ctxs[i]->p.ny;
+        size_t gbytes = 0;
+        int min_nx = INT_MAX;
+        for (int i = first[gi]; i < first[gi + 1]; ++i) {
+            nodes += (long long)ctxs[i]->p.nx * ctxs[i]->p.ny;
+            gbytes += bytes[i];
+            min_nx = std::min(min_nx, ctxs[i]->p.nx);
+        }
         G.nodes = nodes;
+        const GroupPlan gp = plan_group(gbytes, b->storage, kind[first[gi]], tile_x, ctxs + first[gi],
+                                        first[gi + 1] - first[gi]);
+        G.tx = gp.tx;
+        G.variant = gp.variant;
+        const bool xch = gp.variant & cgd::KV_XCH;
         for (int i = first[gi]; i < first[gi + 1]; ++i) {
             lbm_ctx *c = ctxs[i];
             SlotDesc d = c->desc;
-            set_geometry(d, &c->p, c->lay, tx, 1);
-            set_geometry(d, &c->p, c->lay, tx,
-                         plan_strip(pair_nodes, c->p.ny, d.tiles_x, c->p.storage, c->strip_req, ngroups > 1));
+            set_geometry(d, &c->p, c->lay, G.tx, 1, xch);
+            set_geometry(d, &c->p, c->lay, G.tx,
+                         plan_strip(pair_nodes, c->p.ny, d.tiles_x, c->p.storage, c->strip_req, ngroups > 1, xch),
+                         xch);
             d.tile_begin = (int)tiles;
             d.active_steps = INT_MAX;
             if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // batch parity 0 reads the current buffer
             tiles += (long long)d.tiles_x * d.tiles_y;
             G.slots.push_back(d);
-            G.variant = cgd::step_variant(d);
         }
         if (tiles > INT_MAX / 2) {
             lbm_batch_destroy(b);
@@ -857,7 +931,7 @@ static int batch_graph(lbm_batch *b, BatchGroup &G, int parity)
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
     hipError_t le = hipSuccess;
     for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j)
-        le = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (parity + j) & 1, 0,
+        le = cgd::launch_step(b->storage, G.tx, G.d_slots, (int)G.slots.size(), G.tiles, (parity + j) & 1, 0,
                               b->cap_stream, G.variant);
     e = hipStreamEndCapture(b->cap_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -890,7 +964,7 @@ static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n, hi
         n -= kGraphSteps;
     }
     for (; n > 0; --n, ++t) {
-        hipError_t e = cgd::launch_step(b->storage, b->tx, G.d_slots, (int)G.slots.size(), G.tiles, (int)(t & 1), 0,
+        hipError_t e = cgd::launch_step(b->storage, G.tx, G.d_slots, (int)G.slots.size(), G.tiles, (int)(t & 1), 0,
                                         stream, G.variant);
         if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     }

@@ -42,7 +42,10 @@ struct lbm_ctx {
     double *d_partial = nullptr;
     double *d_out = nullptr;
     int64_t steps = 0;
-    int tx = 0, strip_req = 0, tiles = 0;
+    int tx = 0, tiles = 0;              // planned threads per workgroup, tiles of a launch
+    int tx_req = 0, strip_req = 0;      // lbm_set_launch requests (0: planned)
+    int xch_req = -1;                   // lbm_set_exchange request (-1: planned)
+    bool xch = false;                   // planned: the exchange flavour (KV_XCH)
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_len = 0;
     std::string err;
@@ -55,8 +58,21 @@ int validate(const lbm_params *p, std::string &msg);
 Layout layout(const lbm_params *p);
 void fill_desc(const lbm_params *p, cgd::SlotDesc &d);
 int default_tx(int nx, int ny);
-// `paired`: the launch shares the chip with a second one (a batch's lanes).
-int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool paired = false);
+int xch_tx(int nx, int variant);
+// Population bytes of a launch (both buffers of every lattice) beyond which
+// FP32 launches take the exchange flavour of the step (KV_XCH).
+constexpr size_t kXchBytes = 256ull << 20;
+bool plan_exchange(size_t bytes, int storage, int variant);
+// `paired`: the launch shares the chip with a second one (a batch's lanes);
+// `xch`: exchange flavour.
+int plan_strip(long long nodes, int ny, int tiles_x, int storage, int req, bool paired = false, bool xch = false);
+// Launch shape of a group of n lattices stepped together (variant: their
+// step_variant; req_tx: requested threads per workgroup, 0 = planned); the
+// returned variant carries KV_XCH when the group takes the exchange flavour.
+struct GroupPlan {
+    int tx = 64, variant = 0;
+};
+GroupPlan plan_group(size_t bytes, int storage, int variant, int req_tx, lbm_ctx *const *ctxs, int n);
 
 // Lattices stepped together whose buffers exceed the last-level cache are
 // split into contiguous groups that fit (MI355X: 256 MB Infinity Cache) and
@@ -78,6 +94,6 @@ inline std::vector<int> cache_groups(const std::vector<size_t> &bytes, const std
 {
     return cgs::cache_groups(bytes, kind, budget, min_groups);
 }
-void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip);
+void set_geometry(cgd::SlotDesc &d, const lbm_params *p, const Layout &L, int tx, int strip, bool xch);
 
 }  // namespace cgi

@@ -44,13 +44,17 @@ enum : int { F_XPER = 1, F_XOPEN = 2, F_YPER = 4, F_MRT = 8, F_SIGMA = 16, F_FOR
              F_SLIP_HI = 128, F_WET = 256, F_NSC = 512, F_ISO = 1024 };
 enum : int { ST_F32 = 0, ST_F16S = 1, ST_BF16S = 2 };
 
-// A wavefront's 64 lanes hold consecutive columns: it writes the middle 60
-// and reads 2 more on each side for the nearest-neighbour gradient; the
-// second-neighbour gradient reaches 2 columns out and builds ghost rows
-// from 1 column beyond that, so there the wavefront writes 58 and reads 3
-// more on each side.
-__host__ __device__ constexpr int wave_halo(bool iso) { return iso ? 3 : 2; }
-__host__ __device__ constexpr int wave_cols(bool iso) { return 64 - 2 * wave_halo(iso); }
+// A wavefront's 64 lanes hold consecutive columns.  With halo lanes it writes
+// the middle 60 and its 2 outer lanes on each side hold the columns the
+// nearest-neighbour gradient and the ghost rows need; the second-neighbour
+// gradient reaches 2 columns out and builds ghost rows from 1 column beyond
+// that, so there the wavefront writes the middle 58 and its 3 outer lanes on
+// each side hold those columns.  With the exchange (xch, nearest neighbours
+// only) it writes all 64 -- one aligned block of the layout below -- and takes
+// the columns beyond its ends from its neighbour wavefronts or from the halo
+// nodes of its workgroup.
+__host__ __device__ constexpr int wave_halo(bool iso, bool xch) { return xch && !iso ? 0 : (iso ? 3 : 2); }
+__host__ __device__ constexpr int wave_cols(bool iso, bool xch) { return 64 - 2 * wave_halo(iso, xch); }
 
 // ------------------------------------------------------------- descriptor --
 // One lattice ("slot") of a launch.  Built on the host; read with scalar loads.
@@ -63,7 +67,7 @@ struct SlotDesc {
     int tile_begin;               // first tile of this slot in the launch
     int active_steps;             // launches with index >= this leave the slot alone
     int flags;                    // F_*
-    int pad0;
+    uint32_t row_bytes;           // bytes of one row of one colour half (see the layout below)
     float inv_rho0[2];            // 1 / rho0_k (colour field)
     float rho0[2];
     float phi[2][3];              // phi^k by class (equilibrium rest part)
@@ -294,17 +298,36 @@ __device__ __forceinline__ float dec_rest(uint32_t b, float ref, double &exact)
     return dev ? x + ref : x;
 }
 
-// Layout of one colour half of a population buffer.  FP32: nine planes of
-// 4-byte values, direction i at byte i * pb (pb = 4 * plane).  16-bit
-// storage: the rest population (direction 0, which does not stream) as an
-// FP32 plane of 2 * pb bytes first, then the eight moving populations as
-// 16-bit planes, direction i >= 1 at byte (i + 1) * pb (pb = 2 * plane).
-// The FP32 rest population carries each node's exact colour-mass residual
-// (see store18), which 16-bit values cannot hold.
+// Layout of one colour half of a population buffer: rows of blocks, a block
+// holding the nine populations of 64 consecutive nodes of one row (one
+// wavefront's row), direction after direction, 64 consecutive values each.
+// FP32: direction i at byte 256 i of the block (2304 B per block).  16-bit
+// storage: the rest population (direction 0, which does not stream) as 64
+// FP32 values first, then the eight moving populations as 16-bit values,
+// direction i >= 1 at byte 256 + 128 (i - 1) (1280 B per block).  The FP32
+// rest population carries each node's exact colour-mass residual (see
+// store18), which 16-bit values cannot hold.  A wavefront's row of one
+// direction is one aligned 256-byte (128-byte) run, and its whole row of 18
+// populations two runs of 2304 (1280) contiguous bytes, one per colour half:
+// separate planes per direction scattered those 36 accesses over as many
+// distant DRAM pages.  Row pitch = 64 blocks rounded up: row_bytes =
+// (pitch / 64) x block bytes.
 template <int ST> __host__ __device__ constexpr bool rest32() { return ST != ST_F32; }
-template <int ST> __device__ __forceinline__ uint32_t plane_off(int i, uint32_t pb)
+template <int ST> __host__ __device__ constexpr uint32_t blk_bytes() { return rest32<ST>() ? 1280u : 2304u; }
+// offset of direction i inside a block
+template <int ST> __device__ __forceinline__ uint32_t plane_off(int i)
 {
-    return rest32<ST>() ? (i == 0 ? 0u : (uint32_t)(i + 1) * pb) : (uint32_t)i * pb;
+    return rest32<ST>() ? (i == 0 ? 0u : 128u + 128u * (uint32_t)i) : 256u * (uint32_t)i;
+}
+// offset of column x's block plus x's place in a run of stored (16-bit or FP32) values
+template <int ST> __device__ __forceinline__ uint32_t col_off(int x)
+{
+    return (uint32_t)(x >> 6) * blk_bytes<ST>() + (uint32_t)(x & 63) * Codec<ST>::bytes;
+}
+// the same for the FP32 rest population of 16-bit storage
+template <int ST> __device__ __forceinline__ uint32_t rest_col_off(int x)
+{
+    return (uint32_t)(x >> 6) * blk_bytes<ST>() + (uint32_t)(x & 63) * 4u;
 }
 template <int ST> __device__ __forceinline__ long long half_bytes(long long plane)
 {
@@ -335,10 +358,13 @@ __device__ __forceinline__ void store_f32(float v, Rsrc r, uint32_t voff, uint32
 
 // ------------------------------------------------------------ node state --
 struct Node {
-    float n[9];   // colour-blind streamed populations
-    float rr, rb; // colour densities (after boundary completion), correctly rounded
-    float dm;     // exact colour mass minus (rr + rb): the rounding of the FP32 densities
+    float n[9];    // colour-blind streamed populations
     double mr, mb; // exact mass of each colour at the node (what the step must conserve)
+    // colour densities (after boundary completion), correctly rounded
+    __device__ __forceinline__ float rr() const { return (float)mr; }
+    __device__ __forceinline__ float rb() const { return (float)mb; }
+    // exact colour mass minus (rr + rb): the rounding of the FP32 densities
+    __device__ __forceinline__ float dm() const { return (float)(mr + mb - (double)rr() - (double)rb()); }
 };
 
 // Byte offsets of the source columns of one lane for c_x = -1, 0, +1 (i.e.
@@ -347,6 +373,7 @@ struct Node {
 struct XCols {
     uint32_t om, o0, op;   // sources for c_x = -1, 0, +1 (named, not an array: no
                            // dynamically indexed copy on the private stack)
+    uint32_t r0;           // 16-bit storage: the own column's FP32 rest population
     int x;                 // the lane's own column (in range)
     bool inlet, outlet;
     __device__ __forceinline__ uint32_t col(int d) const { return d < 0 ? om : (d == 0 ? o0 : op); }
@@ -382,11 +409,12 @@ __device__ __forceinline__ XCols make_cols(const SlotDesc &S, int x)
         int sx = x - d;
         if (per) sx = wrapi(sx, S.nx);
         else sx = sx < 0 ? 0 : (sx >= S.nx ? S.nx - 1 : sx);
-        const uint32_t o = (uint32_t)sx * Codec<ST>::bytes;
+        const uint32_t o = col_off<ST>(sx);
         if (d < 0) c.om = o;
         else if (d == 0) c.o0 = o;
         else c.op = o;
     }
+    c.r0 = rest_col_off<ST>(x);
     const bool open = S.flags & F_XOPEN;
     c.inlet = open && x == 0;
     c.outlet = open && x == S.nx - 1;
@@ -413,7 +441,7 @@ __device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y)
         int sy = y - d;
         const bool out = sy < 0 || sy >= S.ny;
         if (out && per) sy = wrap_near(sy, S.ny);
-        r.off[d + 1] = (uint32_t)((out && !per) ? y : sy) * (uint32_t)S.pitch * Codec<ST>::bytes;
+        r.off[d + 1] = (uint32_t)((out && !per) ? y : sy) * (uint32_t)S.row_bytes;
     }
     return r;
 }
@@ -430,7 +458,6 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
 {
     using C = Codec<ST>;
     Raw18<ST> raw;
-    const uint32_t pb = (uint32_t)S.plane * C::bytes;
     // walls: populations with c_y = +1 come from beyond the bottom wall in row
     // 0, those with c_y = -1 from beyond the top wall in row ny - 1
     const bool ywall = !(S.flags & F_YPER);
@@ -440,11 +467,11 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
         for (int k = 0; k < 2; ++k)
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                if (rest32<ST>() && i == 0) {   // own node, FP32 plane: offsets twice the 16-bit ones
-                    raw.r0[k] = load_f32raw(h.r[k], 2u * xc.o0, 2u * rw.off[1]);
+                if (rest32<ST>() && i == 0) {   // own node, FP32 run of the block
+                    raw.r0[k] = load_f32raw(h.r[k], xc.r0, rw.off[1]);
                     continue;
                 }
-                raw.v[k * 9 + i] = C::load(h.r[k], xc.col(cx(i)), plane_off<ST>(i, pb) + rw.off[cy(i) + 1]);
+                raw.v[k * 9 + i] = C::load(h.r[k], xc.col(cx(i)), plane_off<ST>(i) + rw.off[cy(i) + 1]);
             }
         return raw;
     }
@@ -452,8 +479,8 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
     for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            if (rest32<ST>() && i == 0) {   // own node, FP32 plane: offsets twice the 16-bit ones
-                raw.r0[k] = load_f32raw(h.r[k], 2u * xc.o0, 2u * rw.off[1]);
+            if (rest32<ST>() && i == 0) {   // own node, FP32 run of the block
+                raw.r0[k] = load_f32raw(h.r[k], xc.r0, rw.off[1]);
                 continue;
             }
             const int dy = cy(i) + 1;
@@ -463,12 +490,151 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
             // (same row and column); free slip the mirrored diagonal of the
             // upstream node of the same row (a wall-normal one bounces back)
             const bool fs = cx(i) != 0 && slip;
-            const uint32_t soff = wall ? plane_off<ST>(fs ? mirror_y(i) : opp(i), pb) + rw.off[1]
-                                       : plane_off<ST>(i, pb) + rw.off[dy];
+            const uint32_t soff = wall ? plane_off<ST>(fs ? mirror_y(i) : opp(i)) + rw.off[1]
+                                       : plane_off<ST>(i) + rw.off[dy];
             const uint32_t voff = wall && !fs ? xc.o0 : xc.col(cx(i));
             raw.v[k * 9 + i] = C::load(h.r[k], voff, soff);
         }
     return raw;
+}
+
+// ------------------------------------------------------------ halo gather --
+// Lanes that write the columns xl .. xr-1 of a row need the colour field
+// (and, with the Navier-Stokes correction, Q) of the columns xl-1 and xr as
+// neighbours, and of xl-2 and xr+1 for ghost rows next to a wall.  Those four
+// "halo nodes" are gathered packed: lane 4 i + n of one load per colour half
+// holds direction i of halo node n (n = 0: xl-1, 1: xl-2, 2: xr+1, 3: xr),
+// read from the address issue() reads for that node and direction.  Their
+// values are then moved (ds_bpermute) to lanes 0, 1, 62 and 63, which stand
+// for halo nodes 0..3 and decode them with finish(): bit for bit what a lane
+// owning that column computes.  With xr = xl + 64 (one wavefront), lanes 0
+// and 63 then hold the two direct neighbours, where the west / east shifts
+// of a row need them.
+__host__ __device__ constexpr int halo_col(int n, int xl, int xr)
+{
+    return n == 0 ? xl - 1 : (n == 1 ? xl - 2 : (n == 2 ? xr + 1 : xr));
+}
+// offset of a lane's halo column from its own wavefront's first column xw
+// (xr = xw + 64): -1, -2, 65, 64 for the lanes 0, 1, 62, 63
+__host__ __device__ constexpr int halo_dx(int n) { return halo_col(n, 0, 64); }
+// halo node a lane stands for (lanes 0, 1, 62, 63; the others repeat 0..3)
+__device__ __forceinline__ int halo_node(int lane) { return lane < 2 ? lane : (lane >= 62 ? lane - 60 : (lane & 3)); }
+
+// A copy of v the compiler cannot see through: lane-dependent values derived
+// from it are recomputed where they are used instead of being hoisted out of
+// the row loop and held in registers all along.
+__device__ __forceinline__ int opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Column a lattice position maps to: periodic wrap, or the nearest column
+// beyond an open face.
+__device__ __forceinline__ int map_col(const SlotDesc &S, int x)
+{
+    return (S.flags & F_XPER) ? wrapi(x, S.nx) : (x < 0 ? 0 : (x >= S.nx ? S.nx - 1 : x));
+}
+
+// Lane-indexed direction tables (a lane's direction is not a compile-time
+// constant there): c_x + 1 and c_y + 1 in 2-bit fields, opposite and mirror
+// directions in 4-bit fields (direction 8 apart).
+__host__ __device__ constexpr uint32_t tab_c(bool ycomp)
+{
+    uint32_t t = 0;
+    for (int i = 0; i < 9; ++i) t |= (uint32_t)((ycomp ? cy(i) : cx(i)) + 1) << (2 * i);
+    return t;
+}
+__host__ __device__ constexpr uint32_t tab_dir(bool mirror)
+{
+    uint32_t t = 0;
+    for (int i = 0; i < 8; ++i) t |= (uint32_t)(mirror ? mirror_y(i) : opp(i)) << (4 * i);
+    return t;
+}
+__host__ __device__ constexpr int cx_of(int i) { return (int)((tab_c(false) >> (2 * i)) & 3u) - 1; }
+__host__ __device__ constexpr int cy_of(int i) { return (int)((tab_c(true) >> (2 * i)) & 3u) - 1; }
+__host__ __device__ constexpr int opp_of(int i) { return i == 8 ? opp(8) : (int)((tab_dir(false) >> (4 * i)) & 15u); }
+__host__ __device__ constexpr int mirror_of(int i) { return i == 8 ? mirror_y(8) : (int)((tab_dir(true) >> (4 * i)) & 15u); }
+__host__ __device__ constexpr bool tables_agree()
+{
+    for (int i = 0; i < 9; ++i)
+        if (cx_of(i) != cx(i) || cy_of(i) != cy(i) || opp_of(i) != opp(i) || mirror_of(i) != mirror_y(i)) return false;
+    return true;
+}
+static_assert(tables_agree(), "lane-indexed direction tables");
+
+// The packed raw values of the halo nodes of one row: v[k] = lane 4 i + n's
+// direction i of halo node n in colour half k (16-bit storage: the FP32 rest
+// population for i = 0, the 16-bit value for i >= 1); lanes 36..63 unused.
+struct HRaw {
+    uint32_t v[2];
+};
+
+// Per-lane source column of the packed gather: lane 4 i + n reads column
+// map(hx_n - c_x,i) (the FP32 rest run of hx_n for i = 0 in 16-bit storage),
+// with hx_n = map(halo_col(n, xl, xr)).
+template <int ST>
+__device__ __forceinline__ uint32_t halo_src_col(const SlotDesc &S, int xl, int xr, int lane)
+{
+    const int i = lane >> 2, n = lane & 3;
+    const int hx = map_col(S, halo_col(n, xl, xr));
+    if (rest32<ST>() && i == 0) return rest_col_off<ST>(hx);
+    return col_off<ST>(map_col(S, hx - cx_of(i > 8 ? 0 : i)));
+}
+
+template <int ST>
+__device__ __forceinline__ HRaw issue_halo(const SlotDesc &S, const Halves &h, uint32_t hsrc, int xl, int xr,
+                                          const RowSrc &rw, int lane)
+{
+    using C = Codec<ST>;
+    HRaw r{{0u, 0u}};
+    lane = opaque(lane);
+    const int i = lane >> 2;
+    if (i > 8) return r;
+    const int cyi = cy_of(i);
+    // source row of direction i (arithmetic on the three row offsets, not a
+    // lane-indexed read of them, which would be a private array)
+    const uint32_t o_mid = rw.off[1];
+    uint32_t off = plane_off<ST>(i) + o_mid + (cyi > 0 ? rw.off[2] - o_mid : 0u) + (cyi < 0 ? rw.off[0] - o_mid : 0u);
+    uint32_t col = hsrc;
+    const bool ywall = !(S.flags & F_YPER);
+    if (ywall && (rw.y == 0 || rw.y == S.ny - 1)) {   // rows next to a wall (uniform branch)
+        // the rules of issue(): beyond a wall no slip takes the node's own
+        // opposite population, free slip the mirrored diagonal of the upstream
+        // node of the same row (a wall-normal one bounces back)
+        const bool wall = cyi > 0 ? rw.y == 0 : (cyi < 0 ? rw.y == S.ny - 1 : false);
+        const bool slip = wall && (S.flags & (cyi > 0 ? F_SLIP_LO : F_SLIP_HI));
+        const bool fs = cx_of(i) != 0 && slip;
+        if (wall) {
+            off = plane_off<ST>(fs ? mirror_of(i) : opp_of(i)) + rw.off[1];
+            if (!fs) col = col_off<ST>(map_col(S, halo_col(lane & 3, xl, xr)));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (rest32<ST>() && i == 0) r.v[k] = load_f32raw(h.r[k], col, off);
+        else r.v[k] = (uint32_t)C::load(h.r[k], col, off);
+    }
+    return r;
+}
+
+// The halo nodes' raw populations in lanes 0, 1, 62, 63 (see halo_node).
+// Every lane must take part (ds_bpermute reads the source lanes' registers).
+template <int ST>
+__device__ __forceinline__ Raw18<ST> halo_raw(const HRaw &hv, int lane)
+{
+    using Rw = typename Codec<ST>::Raw;
+    const int n = halo_node(opaque(lane));
+    Raw18<ST> r;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const uint32_t v = (uint32_t)__builtin_amdgcn_ds_bpermute((4 * i + n) << 2, (int)hv.v[k]);
+            if (rest32<ST>() && i == 0) r.r0[k] = v;
+            else r.v[k * 9 + i] = (Rw)v;
+        }
+    return r;
 }
 
 // Pull gather of one node (Sec. 2 eq. (subop4)), periodic wrap and link
@@ -479,6 +645,9 @@ __device__ __forceinline__ Raw18<ST> issue(const SlotDesc &S, const Halves &h, c
 template <int ST>
 __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, const XCols &xc, const RowSrc &rw)
 {
+    // no contraction: a node finished by its owner and by a halo lane must
+    // come out bit for bit the same
+#pragma clang fp contract(off)
     using C = Codec<ST>;
     Node nd;
     double rho[2];   // colour masses, exact (nine FP32 values sum exactly in FP64)
@@ -515,8 +684,7 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
             }
         }
     }
-    nd.rr = (float)rho[0];
-    nd.rb = (float)rho[1];
+    float rr = (float)rho[0], rb = (float)rho[1];
     if (xc.inlet) {
         const bool red = ((const __attribute__((address_space(1))) int8_t *)S.inlet_color)[rw.y] > 0;
         const float vx = red ? S.u_in[0] : S.u_in[1];
@@ -528,14 +696,14 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
         N[1] = N[3] + (2.f / 3.f) * rin * vx - H;
         N[5] = N[7] - 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f) + 0.5f * H;
         N[8] = N[6] + 0.5f * (N[2] - N[4]) + rin * vx * (1.f / 6.f) + 0.5f * H;
-        nd.rr = red ? rin : 0.f;
-        nd.rb = red ? 0.f : rin;
+        rr = red ? rin : 0.f;
+        rb = red ? 0.f : rin;
     } else if (xc.outlet) {
         const float vr = kn[0] * S.inv_rho0[0], vb = kn[1] * S.inv_rho0[1];
         const float chir = vr / (vr + vb), chib = vb / (vr + vb);
-        nd.rr = chir * S.rho_out[0];
-        nd.rb = chib * S.rho_out[1];
-        const float rho_o = nd.rr + nd.rb;
+        rr = chir * S.rho_out[0];
+        rb = chib * S.rho_out[1];
+        const float rho_o = rr + rb;
         float *N = nd.n;
         const float vx = (N[0] + N[2] + N[4] + 2.f * (N[1] + N[5] + N[8])) / rho_o - 1.f;
         const float H = (S.flags & F_NSC) ? (chir * S.k3[0] + chib * S.k3[1]) * rho_o * vx * (1.f / 3.f) : 0.f;
@@ -544,15 +712,14 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
         N[7] = N[5] + 0.5f * (N[2] - N[4]) - rho_o * vx * (1.f / 6.f) - 0.5f * H;
     }
     if (xc.inlet || xc.outlet) {          // an open boundary prescribes the colour densities
-        rho[0] = (double)nd.rr;
-        rho[1] = (double)nd.rb;
+        rho[0] = (double)rr;
+        rho[1] = (double)rb;
     }
     // The collision relaxes towards an equilibrium of density rr + rb; the
     // residual of their FP32 rounding, identical at every node of a uniform
     // region, would otherwise add or remove mass coherently at every step.
     nd.mr = rho[0];
     nd.mb = rho[1];
-    nd.dm = (float)(rho[0] + rho[1] - (double)nd.rr - (double)nd.rb);
     return nd;
 }
 
@@ -578,6 +745,20 @@ __device__ __forceinline__ void conserve(const Node &nd, float *outr, float *out
     }
 }
 
+// Where one node's populations sit: its column in a run of stored values
+// (col_off), its FP32 rest population (rest_col_off, 16-bit storage) and its
+// row (row_bytes multiple); pos = 2 (y pitch + x), the node's position for the
+// dither of 16-bit storage.
+struct NodeAt {
+    uint32_t col, rcol, row, pos;
+};
+template <int ST>
+__device__ __forceinline__ NodeAt node_at(const SlotDesc &S, int x, int y)
+{
+    return NodeAt{col_off<ST>(x), rest_col_off<ST>(x), (uint32_t)y * (uint32_t)S.row_bytes,
+                  2u * ((uint32_t)y * (uint32_t)S.pitch + (uint32_t)x)};
+}
+
 // Store the 18 post-recolouring populations of one node; mr, mb: the colour
 // masses the node must hold (exact FP64).  16-bit storage: the eight moving
 // pairs are encoded (see the codec), the colour masses of what they decode to
@@ -585,20 +766,19 @@ __device__ __forceinline__ void conserve(const Node &nd, float *outr, float *out
 // its colour's mass, so the stored colour masses of the node are exact to the
 // rounding of one FP32 value each.
 template <int ST>
-__device__ __forceinline__ void store18(const SlotDesc &S, const Halves &h, uint32_t voff, uint32_t rowoff,
-                                        const float *outr, const float *outb, double mr, double mb)
+__device__ __forceinline__ void store18(const SlotDesc &S, const Halves &h, const NodeAt &at, const float *outr,
+                                        const float *outb, double mr, double mb)
 {
     using C = Codec<ST>;
-    const uint32_t pb = (uint32_t)S.plane * C::bytes;
     if constexpr (ST == ST_F32) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            C::store(outr[i], h.r[0], voff, (uint32_t)i * pb + rowoff, S, 0, vclass(i));
-            C::store(outb[i], h.r[1], voff, (uint32_t)i * pb + rowoff, S, 1, vclass(i));
+            C::store(outr[i], h.r[0], at.col, plane_off<ST>(i) + at.row, S, 0, vclass(i));
+            C::store(outb[i], h.r[1], at.col, plane_off<ST>(i) + at.row, S, 1, vclass(i));
         }
     } else {
         // one seed per node from its position and two of the values stored
-        const uint32_t seed = mix32((voff + rowoff) ^ __float_as_uint(outr[1]) ^
+        const uint32_t seed = mix32(at.pos ^ __float_as_uint(outr[1]) ^
                                     __builtin_rotateleft32(__float_as_uint(outb[5]), 13));
         double ar = 0.0, ab = 0.0;
 #pragma unroll
@@ -609,14 +789,14 @@ __device__ __forceinline__ void store18(const SlotDesc &S, const Halves &h, uint
                          q, u, nr, nb);
             ar += (double)nr;
             ab += (double)nb;
-            C::put(q, h.r[0], voff, plane_off<ST>(i, pb) + rowoff);
-            C::put(u, h.r[1], voff, plane_off<ST>(i, pb) + rowoff);
+            C::put(q, h.r[0], at.col, plane_off<ST>(i) + at.row);
+            C::put(u, h.r[1], at.col, plane_off<ST>(i) + at.row);
         }
         const uint32_t r1 = weyl(seed, 18), r2 = weyl(seed, 19);
         const double d1 = CG_CODEC_SR ? (double)(r1 >> 8) * 0x1p-24 : 0.5, d2 = CG_CODEC_SR ? (double)(r2 >> 8) * 0x1p-24 : 0.5;
-        __builtin_amdgcn_raw_buffer_store_b32(enc_rest(mr - ar, S.rest0[0], d1), h.r[0], (int)(2u * voff), (int)(2u * rowoff),
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest(mr - ar, S.rest0[0], d1), h.r[0], (int)at.rcol, (int)at.row,
                                               CG_STORE_POLICY);
-        __builtin_amdgcn_raw_buffer_store_b32(enc_rest(mb - ab, S.rest0[1], d2), h.r[1], (int)(2u * voff), (int)(2u * rowoff),
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest(mb - ab, S.rest0[1], d2), h.r[1], (int)at.rcol, (int)at.row,
                                               CG_STORE_POLICY);
     }
 }
@@ -624,16 +804,15 @@ __device__ __forceinline__ void store18(const SlotDesc &S, const Halves &h, uint
 // Store 18 given populations, rounding to nearest without dither, the rest
 // populations as given.
 template <int ST>
-__device__ __forceinline__ void store18_nearest(const SlotDesc &S, const Halves &h, uint32_t voff, uint32_t rowoff,
-                                                const float *outr, const float *outb)
+__device__ __forceinline__ void store18_nearest(const SlotDesc &S, const Halves &h, const NodeAt &at, const float *outr,
+                                                const float *outb)
 {
     using C = Codec<ST>;
-    const uint32_t pb = (uint32_t)S.plane * C::bytes;
     if constexpr (ST == ST_F32) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            C::store(outr[i], h.r[0], voff, (uint32_t)i * pb + rowoff, S, 0, vclass(i));
-            C::store(outb[i], h.r[1], voff, (uint32_t)i * pb + rowoff, S, 1, vclass(i));
+            C::store(outr[i], h.r[0], at.col, plane_off<ST>(i) + at.row, S, 0, vclass(i));
+            C::store(outb[i], h.r[1], at.col, plane_off<ST>(i) + at.row, S, 1, vclass(i));
         }
     } else {
 #pragma unroll
@@ -641,37 +820,36 @@ __device__ __forceinline__ void store18_nearest(const SlotDesc &S, const Halves 
             uint16_t q, u;
             float nr, nb;
             enc_pair<ST>(S, vclass(i), outr[i], outb[i], 0u, 0u, false, q, u, nr, nb);
-            C::put(q, h.r[0], voff, plane_off<ST>(i, pb) + rowoff);
-            C::put(u, h.r[1], voff, plane_off<ST>(i, pb) + rowoff);
+            C::put(q, h.r[0], at.col, plane_off<ST>(i) + at.row);
+            C::put(u, h.r[1], at.col, plane_off<ST>(i) + at.row);
         }
-        __builtin_amdgcn_raw_buffer_store_b32(enc_rest((double)outr[0], S.rest0[0], 0.5), h.r[0], (int)(2u * voff),
-                                              (int)(2u * rowoff), CG_STORE_POLICY);
-        __builtin_amdgcn_raw_buffer_store_b32(enc_rest((double)outb[0], S.rest0[1], 0.5), h.r[1], (int)(2u * voff),
-                                              (int)(2u * rowoff), CG_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest((double)outr[0], S.rest0[0], 0.5), h.r[0], (int)at.rcol,
+                                              (int)at.row, CG_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b32(enc_rest((double)outb[0], S.rest0[1], 0.5), h.r[1], (int)at.rcol,
+                                              (int)at.row, CG_STORE_POLICY);
     }
 }
 
 // The 18 stored populations of one node, decoded (colour-major).
 template <int ST>
-__device__ __forceinline__ void load_own(const SlotDesc &S, const Halves &h, uint32_t voff, uint32_t rowoff, float *out)
+__device__ __forceinline__ void load_own(const SlotDesc &S, const Halves &h, const NodeAt &at, float *out)
 {
     using C = Codec<ST>;
-    const uint32_t pb = (uint32_t)S.plane * C::bytes;
     if constexpr (ST == ST_F32) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                out[k * 9 + i] = C::dec(C::load(h.r[k], voff, (uint32_t)i * pb + rowoff), S, k, vclass(i));
+                out[k * 9 + i] = C::dec(C::load(h.r[k], at.col, plane_off<ST>(i) + at.row), S, k, vclass(i));
     } else {
         double e;
-        out[0] = dec_rest(load_f32raw(h.r[0], 2u * voff, 2u * rowoff), S.rest0[0], e);
-        out[9] = dec_rest(load_f32raw(h.r[1], 2u * voff, 2u * rowoff), S.rest0[1], e);
+        out[0] = dec_rest(load_f32raw(h.r[0], at.rcol, at.row), S.rest0[0], e);
+        out[9] = dec_rest(load_f32raw(h.r[1], at.rcol, at.row), S.rest0[1], e);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             float N;
-            dec_pair<ST>(S, vclass(i), C::load(h.r[0], voff, plane_off<ST>(i, pb) + rowoff),
-                         C::load(h.r[1], voff, plane_off<ST>(i, pb) + rowoff), N, out[i], out[9 + i]);
+            dec_pair<ST>(S, vclass(i), C::load(h.r[0], at.col, plane_off<ST>(i) + at.row),
+                         C::load(h.r[1], at.col, plane_off<ST>(i) + at.row), N, out[i], out[9 + i]);
         }
     }
 }
@@ -687,6 +865,9 @@ __device__ __forceinline__ float refined_rcp(float x)
 // Colour field, Sec. 2.1.1 eq. (color_field): +1 in pure red.
 __device__ __forceinline__ float color_field(const SlotDesc &S, float rr, float rb)
 {
+    // no contraction: every lane computing a column's colour field (its owner
+    // or a halo lane) must round it the same way
+#pragma clang fp contract(off)
     const float a = rr * S.inv_rho0[0], b = rb * S.inv_rho0[1];
     const float psi = (a - b) * fast_rcp(a + b);
     return b == 0.f ? 1.f : (a == 0.f ? -1.f : psi);   // exactly +-1 in a pure fluid
@@ -695,6 +876,7 @@ __device__ __forceinline__ float color_field(const SlotDesc &S, float rr, float 
 // Velocity with the half-force shift of Guo forcing.
 __device__ __forceinline__ void velocity(const SlotDesc &S, const Node &nd, float rho, float &ux, float &uy)
 {
+#pragma clang fp contract(off)   // the same for a node's owner and a halo lane (Q of the correction)
     const float *N = nd.n;
     const float jx = (N[1] - N[3]) + (N[5] - N[7]) + (N[8] - N[6]);
     const float jy = (N[2] - N[4]) + (N[5] - N[7]) + (N[6] - N[8]);
@@ -782,12 +964,13 @@ __device__ __forceinline__ void wet(const SlotDesc &S, bool bottom, float &Fx, f
 // NSC (compiled in) with nsc (the lattice's flag): the Navier-Stokes
 // correction of Sec. 2.1.3, i.e. the Hermite equilibrium and the MRT source
 // M^-1 C from dqx = dQx/dx, dqy = dQy/dy of Q = sum_k (1.8 alpha_k - 0.8) rho_k u.
-template <bool NSC = false>
-__device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float psi, float Fx, float Fy,
-                                        float *outr, float *outb, bool nsc = false, float dqx = 0.f,
-                                        float dqy = 0.f)
+// Each output pair goes to sink(i, red, blue) as soon as it is formed (in
+// the order i = 0 .. 8), so that a sink that stores can let it go at once.
+template <bool NSC = false, class Sink>
+__device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float psi, float Fx, float Fy, Sink &&sink,
+                                        bool nsc = false, float dqx = 0.f, float dqy = 0.f)
 {
-    const float rr = nd.rr, rb = nd.rb;
+    const float rr = nd.rr(), rb = nd.rb();
     const float rho = rr + rb;
     float ux, uy;
     velocity(S, nd, rho, ux, uy);
@@ -817,7 +1000,7 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
         float t = __builtin_fmaf(-rr, S.phi[0][c], nd.n[i]);
         t = __builtin_fmaf(-rb, S.phi[1][c], t);
         // unit mass of the FP32 rest weights, and the exact mass of the node
-        if (i == 0) t -= rr * S.phi0_eps[0] + rb * S.phi0_eps[1] + nd.dm;
+        if (i == 0) t -= rr * S.phi0_eps[0] + rb * S.phi0_eps[1] + nd.dm();
         if (herm && i != 0)
             neq[i] = t - wgt(i) * (3.f * cu * __builtin_fmaf(hco(i), K, rho) + rho * (4.5f * cu * cu - 1.5f * uu));
         else
@@ -873,35 +1056,76 @@ __device__ __forceinline__ void collide(const SlotDesc &S, const Node &nd, float
     const float cmin = (red_minor ? rr : rb) * irho;    // 0 exactly for an absent colour
     const float cmaj = (red_minor ? rb : rr) * irho;
     const float sgn = red_minor ? 1.f : -1.f;           // the segregation term adds to red
-    if (F2 > 1e-24f) {
-        const float inv = __builtin_amdgcn_rsqf(F2);    // 1/|F|
-        const float Fm = F2 * inv;                       // |F|
-        const float A = (S.flags & F_SIGMA) ? S.sigma94 * w : S.A;
-        const float seg = S.beta * cmin * cmaj;
+    // no gradient (|F| <= 1e-12): neither perturbation nor segregation.  Both
+    // forms are evaluated and selected per lane (uniform control flow, so that
+    // every store of a row is one instruction over the whole wavefront).
+    const bool pert = F2 > 1e-24f;
+    const float inv = pert ? __builtin_amdgcn_rsqf(F2) : 0.f;   // 1/|F|
+    const float Fm = F2 * inv;                                   // |F|
+    const float A = (S.flags & F_SIGMA) ? S.sigma94 * w : S.A;
+    const float seg = S.beta * cmin * cmaj;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const float fc = cx(i) * Fx + cy(i) * Fy;
-            const float nss = ns[i] + A * (wgt(i) * fc * fc * inv - bco(i) * Fm);
-            float sg = 0.f;
-            if (i != 0) {
-                const int c = vclass(i);
-                const float cosphi = fc * inv * (c == 1 ? 1.f : 0.70710678118654752f);
-                sg = seg * cosphi * (rr * S.phi[0][c] + rb * S.phi[1][c]);
-            }
-            const float mino = cmin * nss + sgn * sg;
-            const float majo = nss - mino;
-            outr[i] = red_minor ? mino : majo;
-            outb[i] = red_minor ? majo : mino;
+    for (int i = 0; i < 9; ++i) {
+        const float fc = cx(i) * Fx + cy(i) * Fy;
+        const float nss = ns[i] + A * (wgt(i) * fc * fc * inv - bco(i) * Fm);
+        float sg = 0.f;
+        if (i != 0) {
+            const int c = vclass(i);
+            const float cosphi = fc * inv * (c == 1 ? 1.f : 0.70710678118654752f);
+            sg = seg * cosphi * (rr * S.phi[0][c] + rb * S.phi[1][c]);
         }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const float mino = cmin * ns[i];
-            const float majo = ns[i] - mino;
-            outr[i] = red_minor ? mino : majo;
-            outb[i] = red_minor ? majo : mino;
-        }
+        const float mino_p = cmin * nss + sgn * sg;
+        const float majo_p = nss - mino_p;
+        const float mino_0 = cmin * ns[i];
+        const float majo_0 = ns[i] - mino_0;
+        const float mino = pert ? mino_p : mino_0;
+        const float majo = pert ? majo_p : majo_0;
+        sink(i, red_minor ? mino : majo, red_minor ? majo : mino);
     }
 }
+
+// A sink that keeps the 18 outputs.
+struct Keep18 {
+    float r[9], b[9];
+    __device__ __forceinline__ void operator()(int i, float vr, float vb)
+    {
+        r[i] = vr;
+        b[i] = vb;
+    }
+};
+
+// FP32 storage: the sink stores each output pair as it comes, keeping only
+// the four diagonal pairs, which take the node's colour-mass residual at the
+// end (the exact bookkeeping of conserve(), in the same order).
+struct StoreF32 {
+    const SlotDesc &S;
+    const Halves &h;
+    NodeAt at;
+    double sr, sb;
+    float kr[4], kb[4];
+    __device__ __forceinline__ StoreF32(const SlotDesc &s, const Halves &hh, const NodeAt &a)
+        : S(s), h(hh), at(a), sr(0.0), sb(0.0) {}
+    __device__ __forceinline__ void operator()(int i, float vr, float vb)
+    {
+        sr += (double)vr;
+        sb += (double)vb;
+        if (i < 5) {
+            Codec<ST_F32>::store(vr, h.r[0], at.col, plane_off<ST_F32>(i) + at.row, S, 0, vclass(i));
+            Codec<ST_F32>::store(vb, h.r[1], at.col, plane_off<ST_F32>(i) + at.row, S, 1, vclass(i));
+        } else {
+            kr[i - 5] = vr;
+            kb[i - 5] = vb;
+        }
+    }
+    __device__ __forceinline__ void finish(const Node &nd)
+    {
+        const float qr = (float)((nd.mr - sr) * 0.25), qb = (float)((nd.mb - sb) * 0.25);
+#pragma unroll
+        for (int i = 5; i < 9; ++i) {
+            Codec<ST_F32>::store(kr[i - 5] + qr, h.r[0], at.col, plane_off<ST_F32>(i) + at.row, S, 0, vclass(i));
+            Codec<ST_F32>::store(kb[i - 5] + qb, h.r[1], at.col, plane_off<ST_F32>(i) + at.row, S, 1, vclass(i));
+        }
+    }
+};
 
 }  // namespace cgd

@@ -57,11 +57,364 @@ __device__ __forceinline__ Psi3 psi3(float c) { return Psi3{from_west(c), c, fro
 // Wave tile: 64 lanes cover columns xw-h .. xw+63-h and write the middle
 // 64-2h (h = wave_halo: 2, or 3 with the second-neighbour gradient).
 
-// One fused time step.  Every wavefront owns kOut columns of a strip of rows
-// and marches up the strip on its own (no LDS, no barrier): the colour field
-// of the rows y-1, y, y+1 lives in registers, horizontal neighbours come from
-// the adjacent lanes, and the populations of row y+2 are requested before row
-// y collides.
+// Collision, perturbation and recolouring of one node and the store of its
+// 18 populations.  FP32: each pair is stored as soon as it is formed, the
+// diagonal ones after the exact colour-mass bookkeeping; 16-bit storage
+// (which rounds far coarser and keeps colour mass in its codec) encodes the
+// 18 outputs together.
+template <int ST, bool NSC>
+__device__ __forceinline__ void collide_store(const SlotDesc &S, const Halves &dst, const NodeAt &at, const Node &cur,
+                                              float psi, float Fx, float Fy, bool nsc, float dqx, float dqy)
+{
+    if constexpr (ST == ST_F32) {
+        StoreF32 sk(S, dst, at);
+        if constexpr (NSC) collide<true>(S, cur, psi, Fx, Fy, sk, nsc, dqx, dqy);
+        else collide(S, cur, psi, Fx, Fy, sk);
+        sk.finish(cur);
+    } else {
+        Keep18 k;
+        if constexpr (NSC) collide<true>(S, cur, psi, Fx, Fy, k, nsc, dqx, dqy);
+        else collide(S, cur, psi, Fx, Fy, k);
+        store18<ST>(S, dst, at, k.r, k.b, cur.mr, cur.mb);
+    }
+}
+
+// Colour field of one row: the lane's own value, its west and east
+// neighbours, and the halo nodes' values (lanes 0, 1, 62, 63; see halo_node).
+struct PRow {
+    float w, c, e, h;
+};
+
+// West / east neighbour of each lane's value by a DPP wave shift; lane 0
+// (west) and lane 63 (east) have no neighbour lane and keep h's value, which
+// is where the halo nodes xw-1 and xw+64 sit.
+__device__ __forceinline__ float west_of(float v, float h)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(h), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float east_of(float v, float h)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(h), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// One fused time step with the nearest-neighbour (S2I4) gradient.  A
+// workgroup of W wavefronts owns 64 W consecutive columns of a strip of rows;
+// each wavefront owns 64 of them -- one block of the layout -- and the
+// workgroup marches along the strip row by row: the colour field of the rows
+// y-1, y, y+1 lives in registers, horizontal neighbours come from the
+// adjacent lanes and, at the ends of a wavefront, from its neighbour
+// wavefronts through LDS (one barrier per row) or, at the ends of the
+// workgroup, from the four halo nodes that wavefront 0 gathers beside each
+// row.  The populations of row y+2 are requested before row y collides.
+template <int ST, int W, bool NSC>
+__device__ __forceinline__ void step_nn(const SlotDesc *__restrict__ slots, int nslots, int total_tiles, int parity,
+                                        int launch_idx)
+{
+    const int tile = xcd_tile(blockIdx.x, total_tiles);
+    const SlotDesc S = slots[find_slot(slots, nslots, tile)];
+    if (launch_idx >= S.active_steps) return;   // uniform per workgroup
+
+    // tiles of a lattice run x-fastest: concurrently resident workgroups then
+    // stream neighbouring blocks of the same rows, and vertically adjacent
+    // strips land on the same XCD (shared halo rows in L2)
+    const int lt = tile - S.tile_begin;
+    const int tyi = lt / S.tiles_x;
+    const int txi = lt - tyi * S.tiles_x;
+    const int nx = S.nx, ny = S.ny;
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int x0 = txi * W * 64;                // the workgroup's first column
+    if (x0 >= nx) return;                       // uniform per workgroup
+    // one past its last active column: wavefronts from there on have no
+    // column of the lattice and only keep step with the barriers
+    const int x1 = min(x0 + 64 * W, (nx + 63) & ~63);
+    const int xw = x0 + 64 * wave;
+    const bool active = xw < nx;
+    const int y0 = tyi * S.strip;
+    const int y1 = min(y0 + S.strip, ny);
+    const bool yper = S.flags & F_YPER;
+    const bool xper = S.flags & F_XPER;
+
+    const int xl = xw + lane;                   // the lane's column (may lie beyond nx)
+    const int xg = map_col(S, xl);
+    const bool out_lane = active && xl < nx;
+    const XCols xc = make_cols<ST>(S, xg);
+    const Halves src = halves<ST>(S, parity ? S.buf[1] : S.buf[0]);
+    const Halves dst = halves<ST>(S, parity ? S.buf[0] : S.buf[1]);
+
+    // halo nodes of the workgroup (x0-1, x0-2, x1+1, x1), gathered by
+    // wavefront 0: the packed gather's source column of this lane; the
+    // column each of the lanes 0, 1, 62, 63 stands for (its open-boundary
+    // completion in finish()), formed where it is used
+    const bool halo_wave = wave == 0;
+    const uint32_t hsrc = halo_src_col<ST>(S, x0, x1, lane);
+    auto halo_lane_col = [&]() { return halo_col(halo_node(opaque(lane)), x0, x1); };
+
+    // Row exchange through LDS (W > 1): per row, the colour field (and Q) of
+    // every column of the workgroup, entry 2 + (x - x0), with the halo nodes
+    // at entries 0, 1 (x0-2, x0-1) and 2 + x1 - x0, 3 + x1 - x0; two slots
+    // used in turn, so that a row's values are read before the slot is
+    // written again (one barrier per row).  Each lane then takes the value of
+    // the column its halo_node stands for relative to its own wavefront:
+    // xw-1, xw-2, xw+65, xw+64.
+    constexpr int kRow = 64 * W + 4;
+    constexpr int kFields = NSC ? 3 : 1;
+    __shared__ float xrow[W > 1 ? 2 * kFields * kRow : 1];
+    int slot = 0;
+    auto lds_at = [&](int field, int x) { return (slot * kFields + field) * kRow + 2 + (x - x0); };
+
+    // wall ghost row from the adjacent fluid row (Sec. 2.4 extrapolation):
+    // W-weighted mean over the fluid neighbours, axis : diagonal = 4 : 1,
+    // neighbours beyond an open x face excluded.  Lanes 0 and 63 also form
+    // the ghost values of the columns xw-1 and xw+64.
+    // ghost values of a field c (neighbour values h, see PRow): g in every
+    // lane, gh in lanes 0 and 63 for the columns xw-1 and xw+64 (whose west /
+    // east neighbours xw-2 / xw+65 are in lanes 1 / 62 of h).  The neighbour
+    // values are fetched by every lane before any lane selects: a cross-lane
+    // read under a lane condition would see the inactive lanes as zero.  The
+    // weights are formed here, at wall rows only.
+    auto ghost_vals = [&](float c, float h, float &g, float &gh) {
+        const float w = west_of(c, h), e = east_of(c, h);
+        const int ln = opaque(lane);
+        const int x = xw + ln;
+        const bool in0 = xper || (x >= 0 && x < nx);
+        const bool inw = xper || (x - 1 >= 0 && x - 1 < nx);
+        const bool ine = xper || (x + 1 >= 0 && x + 1 < nx);
+        const float gden = (in0 ? 4.f : 0.f) + (inw ? 1.f : 0.f) + (ine ? 1.f : 0.f);
+        const float ginv = gden > 0.f ? fast_rcp(gden) : 0.f;
+        g = ((in0 ? 4.f * c : 0.f) + (inw ? w : 0.f) + (ine ? e : 0.f)) * ginv;
+        const float h1 = from_east(h), h62 = from_west(h);
+        const float hw = ln == 0 ? h1 : c;
+        const float he = ln == 0 ? c : h62;
+        const int hxl = xw + halo_dx(halo_node(ln));
+        const bool hin0 = xper || (hxl >= 0 && hxl < nx);
+        const bool hinw = xper || (hxl - 1 >= 0 && hxl - 1 < nx);
+        const bool hine = xper || (hxl + 1 >= 0 && hxl + 1 < nx);
+        const float hgden = (hin0 ? 4.f : 0.f) + (hinw ? 1.f : 0.f) + (hine ? 1.f : 0.f);
+        const float hginv = hgden > 0.f ? fast_rcp(hgden) : 0.f;
+        gh = ((hin0 ? 4.f * h : 0.f) + (hinw ? hw : 0.f) + (hine ? he : 0.f)) * hginv;
+    };
+    auto prow = [&](float c, float h) { return PRow{west_of(c, h), c, east_of(c, h), h}; };
+    auto ghost = [&](const PRow &f) -> PRow {
+        float g, gh;
+        ghost_vals(f.c, f.h, g, gh);
+        return PRow{west_of(g, gh), g, east_of(g, gh), gh};
+    };
+    auto real_row = [&](int r) { return yper ? wrap_near(r, ny) : r; };
+    auto gathered = [&](int r) { return yper || (r >= 0 && r < ny); };
+
+    // Navier-Stokes correction (Sec. 2.1.3): Q = sum_k (1.8 alpha_k - 0.8)
+    // rho_k u per node, and per row the two partial sums its stencil needs:
+    // d = Q_x(east) - Q_x(west) and s = Q_y / 3 + (Q_y(east) + Q_y(west)) / 12,
+    // so that dQx/dx = d(y) / 3 + (d(y-1) + d(y+1)) / 12 and
+    // dQy/dy = s(y+1) - s(y-1) (the stencil of eq. (colorGradient)).  Ghost
+    // rows beyond a wall take the colour field's extrapolation of Q.  hx, hy:
+    // the neighbour values of Q (as PRow::h).
+    const bool nsc = NSC && (S.flags & F_NSC);
+    struct QRow {
+        float d, s, hx, hy;
+    };
+    // (no contraction in these: every copy the compiler inlines -- the first
+    // rows of a strip, the rest, a halo lane -- must round alike, so that
+    // results do not depend on the strip height)
+    auto qrow = [&](float qx, float qy, float hqx, float hqy) -> QRow {
+#pragma clang fp contract(off)
+        return QRow{east_of(qx, hqx) - west_of(qx, hqx),
+                    (1.f / 3.f) * qy + (1.f / 12.f) * (east_of(qy, hqy) + west_of(qy, hqy)), hqx, hqy};
+    };
+    auto qnode = [&](const Node &nd, float &qx, float &qy) {
+#pragma clang fp contract(off)
+        float ux, uy;
+        velocity(S, nd, nd.rr() + nd.rb(), ux, uy);
+        const float a = -(nd.rr() * S.k3[0] + nd.rb() * S.k3[1]);
+        qx = a * ux;
+        qy = a * uy;
+    };
+    // the ghost row's Q from the adjacent real row (its nodes and neighbour Q)
+    auto qghost = [&](const Node &adj, const QRow &qa) -> QRow {
+        float qx, qy, gx, gy, ghx, ghy;
+        qnode(adj, qx, qy);
+        ghost_vals(qx, qa.hx, gx, ghx);
+        ghost_vals(qy, qa.hy, gy, ghy);
+        return qrow(gx, gy, ghx, ghy);
+    };
+
+    // one gathered row: the lanes' populations and (wavefront 0) the halo nodes'
+    struct Pend {
+        Raw18<ST> m;
+        HRaw h;
+    };
+    auto issue_row = [&](const RowSrc &rw) -> Pend {
+        Pend p;
+        if (active) p.m = issue<ST>(S, src, xc, rw);
+        if (halo_wave) p.h = issue_halo<ST>(S, src, hsrc, x0, x1, rw, lane);
+        return p;
+    };
+    // A gathered row's own values: node, colour field, Q (lanes' columns);
+    // and the halo nodes' colour field and Q in lanes 0, 1, 62, 63 of
+    // wavefront 0.
+    struct Own {
+        Node nd;
+        float c, qx, qy;
+        float hc, hqx, hqy;
+    };
+    auto finish_own = [&](const Pend &p, const RowSrc &rw) -> Own {
+        Own o{};
+        if (active) {
+            o.nd = finish<ST>(S, p.m, xc, rw);
+            o.c = color_field(S, o.nd.rr(), o.nd.rb());
+            if (nsc) qnode(o.nd, o.qx, o.qy);
+        }
+        if (halo_wave) {
+            XCols hxc{};
+            if (S.flags & F_XOPEN) {
+                const int hxg = map_col(S, halo_lane_col());
+                hxc.inlet = hxg == 0;
+                hxc.outlet = hxg == nx - 1;
+            }
+            const Node hn = finish<ST>(S, halo_raw<ST>(p.h, lane), hxc, rw);
+            o.hc = color_field(S, hn.rr(), hn.rb());
+            if (nsc) qnode(hn, o.hqx, o.hqy);
+        }
+        return o;
+    };
+    // Neighbour values of a row (PRow::h and QRow::hx, hy).  One wavefront:
+    // its own halo nodes.  Several: every wavefront puts its row and
+    // wavefront 0 the halo nodes into the LDS slot, then (after the barrier)
+    // each lane reads the column it stands for.
+    auto publish = [&](const Own &o) {
+        if constexpr (W > 1) {
+            const int hx = halo_lane_col();
+            const bool hl = halo_wave && (lane < 2 || lane >= 62);
+            if (active) xrow[lds_at(0, xl)] = o.c;
+            if (hl) xrow[lds_at(0, hx)] = o.hc;
+            if (nsc) {
+                if (active) {
+                    xrow[lds_at(1, xl)] = o.qx;
+                    xrow[lds_at(2, xl)] = o.qy;
+                }
+                if (hl) {
+                    xrow[lds_at(1, hx)] = o.hqx;
+                    xrow[lds_at(2, hx)] = o.hqy;
+                }
+            }
+        }
+    };
+    auto take = [&](const Own &o, PRow &pr, QRow &qr) {
+        float h = o.hc, hqx = o.hqx, hqy = o.hqy;
+        if constexpr (W > 1) {
+            const int x = xw + halo_dx(halo_node(opaque(lane)));
+            h = xrow[lds_at(0, x)];
+            if (nsc) {
+                hqx = xrow[lds_at(1, x)];
+                hqy = xrow[lds_at(2, x)];
+            }
+            slot ^= 1;
+        }
+        pr = prow(o.c, h);
+        if (nsc) qr = qrow(o.qx, o.qy, hqx, hqy);
+    };
+    auto sync = [&]() {
+        if constexpr (W > 1) __syncthreads();
+    };
+
+    // Even strips march up, odd strips march down: the two strips on either
+    // side of a strip boundary then read their shared halo rows at the same
+    // time (both at the start or both at the end), so the second read hits L2.
+    const int d = (tyi & 1) ? -1 : 1;
+    const int ys = d > 0 ? y0 : y1 - 1;        // first row written
+    const int ye = d > 0 ? y1 : y0 - 1;        // one past the last row written
+
+    // prologue: the row behind the first one, and the first one
+    PRow pb, p0;                                // colour field of rows y-d and y
+    QRow qb{}, q0{};                            // Q partial sums of rows y-d and y (NSC)
+    Node cur;
+    {
+        const bool have_b = gathered(ys - d);
+        const RowSrc rwb = make_row<ST>(S, have_b ? real_row(ys - d) : ys);
+        Pend rb;
+        if (have_b) rb = issue_row(rwb);
+        const RowSrc rw0 = make_row<ST>(S, ys);
+        const Pend r0 = issue_row(rw0);
+        if (have_b) {
+            const Own ob = finish_own(rb, rwb);
+            publish(ob);
+            sync();
+            take(ob, pb, qb);
+        }
+        const Own o0 = finish_own(r0, rw0);
+        cur = o0.nd;
+        publish(o0);
+        sync();
+        take(o0, p0, q0);
+        if (!have_b) {                          // the row behind lies beyond a wall
+            pb = ghost(p0);
+            if (nsc) qb = qghost(cur, q0);
+        }
+    }
+    bool have_p = gathered(ys + d);
+    RowSrc rwp = make_row<ST>(S, have_p ? real_row(ys + d) : ys);
+    Pend pend;
+    if (have_p) pend = issue_row(rwp);
+
+    const float fd = (float)d;
+    for (int y = ys; y != ye; y += d) {
+        Node nxt;
+        PRow pa;                                // colour field of row y+d (ahead)
+        QRow qa{};
+        Own oa;
+        if (have_p) {
+            oa = finish_own(pend, rwp);
+            nxt = oa.nd;
+            publish(oa);
+        }
+        // request row y+2d now; it arrives while row y collides
+        const int r2 = y + 2 * d;
+        const bool had_p = have_p;
+        have_p = (d > 0 ? r2 <= y1 : r2 >= y0 - 1) && gathered(r2);
+        if (have_p) {
+            rwp = make_row<ST>(S, real_row(r2));
+            pend = issue_row(rwp);
+        }
+        if (had_p) {
+            sync();
+            take(oa, pa, qa);
+        } else {
+            pa = ghost(p0);                     // row y+d lies beyond a wall
+            if (nsc) qa = qghost(cur, q0);
+        }
+        if (out_lane) {
+            // S2I4 gradient, Sec. 2.2 eq. (colorGradient): xi = 1/3 axis, 1/12 diagonal;
+            // rows y+1 / y-1 are ahead / behind when marching up, the reverse when down
+            float Fx = (1.f / 3.f) * (p0.e - p0.w) + (1.f / 12.f) * ((pa.e - pa.w) + (pb.e - pb.w));
+            float Fy = fd * ((1.f / 3.f) * (pa.c - pb.c) + (1.f / 12.f) * ((pa.e + pa.w) - (pb.e + pb.w)));
+            if ((S.flags & F_WET) && (y == 0 || y == ny - 1)) wet(S, y == 0, Fx, Fy);
+            const NodeAt at{xc.o0, xc.r0, (uint32_t)y * (uint32_t)S.row_bytes,
+                            2u * ((uint32_t)y * (uint32_t)S.pitch + (uint32_t)xg)};
+            float dqx = 0.f, dqy = 0.f;
+            if constexpr (NSC) {
+                dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
+                dqy = fd * (qa.s - qb.s);
+            }
+            collide_store<ST, NSC>(S, dst, at, cur, p0.c, Fx, Fy, nsc, dqx, dqy);
+        }
+        pb = p0;
+        p0 = pa;
+        qb = q0;
+        q0 = qa;
+        cur = nxt;
+    }
+}
+
+// One fused time step, halo lanes: every wavefront owns the middle 60 of its
+// 64 lanes' columns (58 with the second-neighbour gradient) in a strip of
+// rows and marches along the strip on its own (no LDS, no barrier): the
+// colour field of the rows y-1, y, y+1 (y-2 .. y+2) lives in registers,
+// horizontal neighbours come from the adjacent lanes, the 2 (3) outer lanes
+// on each side holding halo columns, and the populations of row y+2 (y+3)
+// are requested before row y collides.  A wavefront's stores then cover
+// parts of two blocks: cheap while the lattice stays in the cache, costly
+// (partial lines) beyond it, where step_nn takes over.
 template <int ST, int W, bool NSC, bool ISO>
 __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
                                           int parity, int launch_idx)
@@ -78,7 +431,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
     const int txi = lt - tyi * S.tiles_x;
     const int nx = S.nx, ny = S.ny;
     const int lane = threadIdx.x & 63;
-    constexpr int kHalo = wave_halo(ISO), kOut = wave_cols(ISO);
+    constexpr int kHalo = wave_halo(ISO, false), kOut = wave_cols(ISO, false);
     const int xw = (txi * W + (int)(threadIdx.x >> 6)) * kOut;
     if (xw >= nx) return;                      // uniform per wavefront
     const int y0 = tyi * S.strip;
@@ -118,13 +471,16 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
     struct QRow {
         float d, s;
     };
+    // (no contraction: every inlined copy must round alike, see step_nn)
     auto qrow = [&](float qx, float qy) -> QRow {
+#pragma clang fp contract(off)
         return QRow{from_east(qx) - from_west(qx), (1.f / 3.f) * qy + (1.f / 12.f) * (from_east(qy) + from_west(qy))};
     };
     auto qnode = [&](const Node &nd, float &qx, float &qy) {
+#pragma clang fp contract(off)
         float ux, uy;
-        velocity(S, nd, nd.rr + nd.rb, ux, uy);
-        const float a = -(nd.rr * S.k3[0] + nd.rb * S.k3[1]);
+        velocity(S, nd, nd.rr() + nd.rb(), ux, uy);
+        const float a = -(nd.rr() * S.k3[0] + nd.rb() * S.k3[1]);
         qx = a * ux;
         qy = a * uy;
     };
@@ -200,11 +556,11 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
             const Raw18<ST> r0 = issue<ST>(S, src, xc, w0);
             if (ha1) ra1 = issue<ST>(S, src, xc, wa1);
             cur = finish<ST>(S, r0, xc, w0);
-            c0 = color_field(S, cur.rr, cur.rb);
+            c0 = color_field(S, cur.rr(), cur.rb());
             if (nsc) q0 = qreal(cur);
             if (hb1) {
                 const Node t = finish<ST>(S, rb1, xc, wb1);
-                cb1 = color_field(S, t.rr, t.rb);
+                cb1 = color_field(S, t.rr(), t.rb());
                 if (nsc) qb = qreal(t);
             } else {
                 cb1 = ghost1(c0);
@@ -212,13 +568,13 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
             }
             if (hb2) {
                 const Node t = finish<ST>(S, rb2, xc, wb2);
-                cb2 = color_field(S, t.rr, t.rb);
+                cb2 = color_field(S, t.rr(), t.rb());
             } else {
                 cb2 = hb1 ? ghost1(cb1) : cb1;   // beyond a wall: distance 1, or the inner ghost row
             }
             if (ha1) {
                 nxt = finish<ST>(S, ra1, xc, wa1);
-                ca1 = color_field(S, nxt.rr, nxt.rb);
+                ca1 = color_field(S, nxt.rr(), nxt.rb());
                 if (nsc) qa = qreal(nxt);
             } else {
                 ca1 = ghost1(c0);
@@ -229,7 +585,6 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         Raw18<ST> pend;
         if (hp) pend = issue<ST>(S, src, xc, make_row<ST>(S, real_row(ys + 2 * d)));
 
-        const uint32_t rowbytes = (uint32_t)S.pitch * Codec<ST>::bytes;
         const float fd = (float)d;
         for (int y = ys; y != ye; y += d) {
             Node nn;                           // row y+2d
@@ -237,7 +592,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
             QRow q2{};
             if (hp) {
                 nn = finish<ST>(S, pend, xc, make_row<ST>(S, real_row(y + 2 * d)));
-                ca2 = color_field(S, nn.rr, nn.rb);
+                ca2 = color_field(S, nn.rr(), nn.rb());
                 if (nsc) q2 = qreal(nn);
             } else if (gathered(y + d)) {       // row y+2d is the ghost row next to a wall
                 ca2 = ghost1(ca1);
@@ -260,16 +615,14 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
                                  2.f * ((1.f / 60.f) * (pa2.c - pb2.c) + (2.f / 315.f) * (sx1(pa2) - sx1(pb2)) +
                                         (1.f / 5040.f) * (sx2(pa2) - sx2(pb2))));
                 if ((S.flags & F_WET) && (y == 0 || y == ny - 1)) wet(S, y == 0, Fx, Fy);
-                float outr[9], outb[9];
+                const NodeAt at{xc.o0, xc.r0, (uint32_t)y * (uint32_t)S.row_bytes,
+                                2u * ((uint32_t)y * (uint32_t)S.pitch + (uint32_t)xg)};
+                float dqx = 0.f, dqy = 0.f;
                 if constexpr (NSC) {
-                    const float dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
-                    const float dqy = fd * (qa.s - qb.s);
-                    collide<true>(S, cur, c0, Fx, Fy, outr, outb, nsc, dqx, dqy);
-                } else {
-                    collide(S, cur, c0, Fx, Fy, outr, outb);
+                    dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
+                    dqy = fd * (qa.s - qb.s);
                 }
-                if (ST == ST_F32) conserve(cur, outr, outb);
-                store18<ST>(S, dst, xc.o0, (uint32_t)y * rowbytes, outr, outb, cur.mr, cur.mb);
+                collide_store<ST, NSC>(S, dst, at, cur, c0, Fx, Fy, nsc, dqx, dqy);
             }
             cb2 = cb1;
             cb1 = c0;
@@ -297,11 +650,11 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         const Raw18<ST> r0 = issue<ST>(S, src, xc, rw0);
         if (have_b) {
             const Node t = finish<ST>(S, rb, xc, rwb);
-            pb = psi3(color_field(S, t.rr, t.rb));
+            pb = psi3(color_field(S, t.rr(), t.rb()));
             if (nsc) qb = qreal(t);
         }
         cur = finish<ST>(S, r0, xc, rw0);
-        p0 = psi3(color_field(S, cur.rr, cur.rb));
+        p0 = psi3(color_field(S, cur.rr(), cur.rb()));
         if (nsc) q0 = qreal(cur);
         if (!have_b) {                         // the row behind lies beyond a wall
             pb = ghost(p0);
@@ -313,7 +666,6 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
     Raw18<ST> pend;
     if (have_p) pend = issue<ST>(S, src, xc, rwp);
 
-    const uint32_t rowbytes = (uint32_t)S.pitch * Codec<ST>::bytes;
     const float fd = (float)d;
     for (int y = ys; y != ye; y += d) {
         Node nxt;
@@ -321,7 +673,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         QRow qa{};
         if (have_p) {
             nxt = finish<ST>(S, pend, xc, rwp);
-            pa = psi3(color_field(S, nxt.rr, nxt.rb));
+            pa = psi3(color_field(S, nxt.rr(), nxt.rb()));
             if (nsc) qa = qreal(nxt);
         } else {
             pa = ghost(p0);                    // row y+d lies beyond a wall
@@ -340,16 +692,14 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
             float Fx = (1.f / 3.f) * (p0.e - p0.w) + (1.f / 12.f) * ((pa.e - pa.w) + (pb.e - pb.w));
             float Fy = fd * ((1.f / 3.f) * (pa.c - pb.c) + (1.f / 12.f) * ((pa.e + pa.w) - (pb.e + pb.w)));
             if ((S.flags & F_WET) && (y == 0 || y == ny - 1)) wet(S, y == 0, Fx, Fy);
-            float outr[9], outb[9];
+            const NodeAt at{xc.o0, xc.r0, (uint32_t)y * (uint32_t)S.row_bytes,
+                            2u * ((uint32_t)y * (uint32_t)S.pitch + (uint32_t)xg)};
+            float dqx = 0.f, dqy = 0.f;
             if constexpr (NSC) {
-                const float dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
-                const float dqy = fd * (qa.s - qb.s);
-                collide<true>(S, cur, p0.c, Fx, Fy, outr, outb, nsc, dqx, dqy);
-            } else {
-                collide(S, cur, p0.c, Fx, Fy, outr, outb);
+                dqx = (1.f / 3.f) * q0.d + (1.f / 12.f) * (qa.d + qb.d);
+                dqy = fd * (qa.s - qb.s);
             }
-            if (ST == ST_F32) conserve(cur, outr, outb);   // 16-bit storage rounds far coarser
-            store18<ST>(S, dst, xc.o0, (uint32_t)y * rowbytes, outr, outb, cur.mr, cur.mb);
+            collide_store<ST, NSC>(S, dst, at, cur, p0.c, Fx, Fy, nsc, dqx, dqy);
         }
         pb = p0;
         p0 = pa;
@@ -359,22 +709,32 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
     }
 }
 
-template <int ST, int W, bool NSC, bool ISO>
-__global__ void __launch_bounds__(64 * W) k_step(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
-                                                 int parity, int launch_idx)
+// Register budgets: the variants without the Navier-Stokes correction fit
+// 128 VGPRs, i.e. 4 wavefronts per SIMD, without spilling and are capped
+// there; the corrected ones keep their natural allocation (3 per SIMD; the
+// cap would spill to scratch).
+// KV: variant bits (KV_NSC, KV_ISO, KV_XCH of cg_kernels.hpp).
+template <int ST, int W, int KV>
+__device__ __forceinline__ void step_any(const SlotDesc *__restrict__ slots, int nslots, int total_tiles, int parity,
+                                         int launch_idx)
 {
-    step_body<ST, W, NSC, ISO>(slots, nslots, total_tiles, parity, launch_idx);
+    constexpr bool NSC = KV & KV_NSC, ISO = KV & KV_ISO;
+    if constexpr ((KV & KV_XCH) && !ISO) step_nn<ST, W, NSC>(slots, nslots, total_tiles, parity, launch_idx);
+    else step_body<ST, W, NSC, ISO>(slots, nslots, total_tiles, parity, launch_idx);
 }
 
-// The FP32 second-neighbour variant without the correction, its register
-// budget capped at 4 waves per SIMD (128 VGPRs, reached without spilling):
-// 9% faster than at the 3 waves its natural allocation allows.  The 16-bit
-// and corrected variants would spill to scratch under the same cap.
-template <int ST, int W>
+template <int ST, int W, int KV>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_step_iso4(const SlotDesc *__restrict__ slots, int nslots, int total_tiles, int parity, int launch_idx)
+k_step(const SlotDesc *__restrict__ slots, int nslots, int total_tiles, int parity, int launch_idx)
 {
-    step_body<ST, W, false, true>(slots, nslots, total_tiles, parity, launch_idx);
+    step_any<ST, W, KV>(slots, nslots, total_tiles, parity, launch_idx);
+}
+
+template <int ST, int W, int KV>
+__global__ void __launch_bounds__(64 * W) k_step_nsc(const SlotDesc *__restrict__ slots, int nslots, int total_tiles,
+                                                     int parity, int launch_idx)
+{
+    step_any<ST, W, KV>(slots, nslots, total_tiles, parity, launch_idx);
 }
 
 // ---------------------------------------------------------------- init --
@@ -403,8 +763,7 @@ __global__ void __launch_bounds__(256) k_init(const SlotDesc *__restrict__ sd, c
                 e[k][i] = rk[k] * (S.phi[k][vclass(i)] + wgt(i) * (lin + 4.5f * cu * cu - 1.5f * uu));
                 if (i == 0) e[k][i] += rk[k] * S.phi0_eps[k];
             }
-        store18<ST>(S, dst, (uint32_t)x * Codec<ST>::bytes, (uint32_t)y * S.pitch * Codec<ST>::bytes, e[0], e[1],
-                    (double)rk[0], (double)rk[1]);
+        store18<ST>(S, dst, node_at<ST>(S, x, y), e[0], e[1], (double)rk[0], (double)rk[1]);
     }
 }
 
@@ -427,26 +786,26 @@ __global__ void __launch_bounds__(256) k_moments(const SlotDesc *__restrict__ sd
         const XCols xc = make_cols<ST>(S, x);
         const RowSrc rw = make_row<ST>(S, y);
         const Node nd = finish<ST>(S, issue<ST>(S, src, xc, rw), xc, rw);
-        const float rho = nd.rr + nd.rb;
+        const float rho = nd.rr() + nd.rb();
         float ux, uy;
         velocity(S, nd, rho, ux, uy);
-        const float p = nd.rr * S.cs2[0] + nd.rb * S.cs2[1];
+        const float p = nd.rr() * S.cs2[0] + nd.rb() * S.cs2[1];
         if (fields) {
-            fields[c] = nd.rr;
-            fields[n + c] = nd.rb;
+            fields[c] = nd.rr();
+            fields[n + c] = nd.rb();
             fields[2 * n + c] = ux;
             fields[3 * n + c] = uy;
             fields[4 * n + c] = p;
         }
-        const bool finite = __builtin_isfinite(nd.rr) && __builtin_isfinite(nd.rb) && __builtin_isfinite(ux) &&
+        const bool finite = __builtin_isfinite(nd.rr()) && __builtin_isfinite(nd.rb()) && __builtin_isfinite(ux) &&
                             __builtin_isfinite(uy);
         if (!finite) {
             acc[7] += 1.0;
             continue;
         }
-        acc[0] += (double)nd.rr;
-        acc[1] += (double)nd.rb;
-        acc[2] += 0.5 * (1.0 + (double)color_field(S, nd.rr, nd.rb));
+        acc[0] += (double)nd.rr();
+        acc[1] += (double)nd.rb();
+        acc[2] += 0.5 * (1.0 + (double)color_field(S, nd.rr(), nd.rb()));
         const double um = sqrt((double)ux * ux + (double)uy * uy);
         acc[8] = um > acc[8] ? um : acc[8];
         if (r_in > 0.0 || r_out > 0.0) {
@@ -520,7 +879,6 @@ template <int ST>
 __global__ void __launch_bounds__(256) k_get_pops(const SlotDesc *__restrict__ sd, int which,
                                                   float *__restrict__ out)
 {
-    using C = Codec<ST>;
     const SlotDesc S = *sd;
     const long long n = (long long)S.nx * S.ny;
     const Halves src = halves<ST>(S, which ? S.buf[1] : S.buf[0]);
@@ -528,7 +886,7 @@ __global__ void __launch_bounds__(256) k_get_pops(const SlotDesc *__restrict__ s
          c += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(c / S.nx), x = (int)(c - (long long)y * S.nx);
         float v[18];
-        load_own<ST>(S, src, (uint32_t)x * C::bytes, (uint32_t)y * S.pitch * C::bytes, v);
+        load_own<ST>(S, src, node_at<ST>(S, x, y), v);
 #pragma unroll
         for (int j = 0; j < 18; ++j) out[(long long)j * n + c] = v[j];
     }
@@ -538,7 +896,6 @@ template <int ST>
 __global__ void __launch_bounds__(256) k_set_pops(const SlotDesc *__restrict__ sd, int which,
                                                   const float *__restrict__ in)
 {
-    using C = Codec<ST>;
     const SlotDesc S = *sd;
     const long long n = (long long)S.nx * S.ny;
     const Halves dst = halves<ST>(S, which ? S.buf[1] : S.buf[0]);
@@ -551,7 +908,7 @@ __global__ void __launch_bounds__(256) k_set_pops(const SlotDesc *__restrict__ s
             r[i] = in[(long long)i * n + c];
             b[i] = in[(long long)(9 + i) * n + c];
         }
-        store18_nearest<ST>(S, dst, (uint32_t)x * C::bytes, (uint32_t)y * S.pitch * C::bytes, r, b);
+        store18_nearest<ST>(S, dst, node_at<ST>(S, x, y), r, b);
     }
 }
 
@@ -564,24 +921,31 @@ __global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uin
 }
 
 // ------------------------------------------------------------- launchers --
-template <int ST, bool NSC, bool ISO>
+template <int ST, int KV>
 static hipError_t step_v(int tx, const SlotDesc *d, int nslots, int tiles, int parity, int idx, hipStream_t s)
 {
-    if constexpr (ST == ST_F32 && ISO && !NSC) {
+#define CG_STEP(K, W)                                                                                        \
+    hipLaunchKernelGGL((K<ST, W, KV>), dim3(tiles), dim3(64 * W), 0, s, d, nslots, tiles, parity, idx)
+    if constexpr (KV & KV_NSC) {
         switch (tx) {
-        case 64: hipLaunchKernelGGL((k_step_iso4<ST, 1>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
-        case 128: hipLaunchKernelGGL((k_step_iso4<ST, 2>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
-        case 256: hipLaunchKernelGGL((k_step_iso4<ST, 4>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
+        case 64: CG_STEP(k_step_nsc, 1); break;
+        case 128: CG_STEP(k_step_nsc, 2); break;
+        case 256: CG_STEP(k_step_nsc, 4); break;
+        case 512: CG_STEP(k_step_nsc, 8); break;
+        case 1024: CG_STEP(k_step_nsc, 16); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (tx) {
-        case 64: hipLaunchKernelGGL((k_step<ST, 1, NSC, ISO>), dim3(tiles), dim3(64), 0, s, d, nslots, tiles, parity, idx); break;
-        case 128: hipLaunchKernelGGL((k_step<ST, 2, NSC, ISO>), dim3(tiles), dim3(128), 0, s, d, nslots, tiles, parity, idx); break;
-        case 256: hipLaunchKernelGGL((k_step<ST, 4, NSC, ISO>), dim3(tiles), dim3(256), 0, s, d, nslots, tiles, parity, idx); break;
+        case 64: CG_STEP(k_step, 1); break;
+        case 128: CG_STEP(k_step, 2); break;
+        case 256: CG_STEP(k_step, 4); break;
+        case 512: CG_STEP(k_step, 8); break;
+        case 1024: CG_STEP(k_step, 16); break;
         default: return hipErrorInvalidValue;
         }
     }
+#undef CG_STEP
     return hipGetLastError();
 }
 
@@ -590,10 +954,12 @@ static hipError_t step_st(int tx, const SlotDesc *d, int nslots, int tiles, int 
                           int variant)
 {
     switch (variant) {
-    case 0: return step_v<ST, false, false>(tx, d, nslots, tiles, parity, idx, s);
-    case KV_NSC: return step_v<ST, true, false>(tx, d, nslots, tiles, parity, idx, s);
-    case KV_ISO: return step_v<ST, false, true>(tx, d, nslots, tiles, parity, idx, s);
-    case KV_NSC | KV_ISO: return step_v<ST, true, true>(tx, d, nslots, tiles, parity, idx, s);
+    case 0: return step_v<ST, 0>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_NSC: return step_v<ST, KV_NSC>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_ISO: return step_v<ST, KV_ISO>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_NSC | KV_ISO: return step_v<ST, KV_NSC | KV_ISO>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_XCH: return step_v<ST, KV_XCH>(tx, d, nslots, tiles, parity, idx, s);
+    case KV_XCH | KV_NSC: return step_v<ST, KV_XCH | KV_NSC>(tx, d, nslots, tiles, parity, idx, s);
     }
     return hipErrorInvalidValue;
 }

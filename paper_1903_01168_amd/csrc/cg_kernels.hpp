@@ -8,8 +8,12 @@ namespace cgd {
 // Variants of the step kernel: KV_NSC carries the Navier-Stokes correction
 // (Sec. 2.1.3; applied to the lattices whose descriptor has F_NSC, the others
 // are stepped as by the plain variant), KV_ISO the second-neighbour colour
-// gradient for every lattice of the launch.
-enum : int { KV_NSC = 1, KV_ISO = 2 };
+// gradient for every lattice of the launch.  KV_XCH (nearest-neighbour
+// gradient only) is a launch choice, not a lattice property: wavefronts own
+// whole 64-column blocks and take their edge columns from each other through
+// LDS (full-line stores, for lattices beyond the cache), instead of holding
+// halo columns in their own outer lanes.  Both give the same bits.
+enum : int { KV_NSC = 1, KV_ISO = 2, KV_XCH = 4 };
 // The variant a lattice needs alone.
 inline int step_variant(const SlotDesc &d)
 {

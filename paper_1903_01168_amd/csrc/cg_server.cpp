@@ -137,7 +137,7 @@ struct GpuBackend : Backend {
     struct Chunk {
         hipGraphExec_t graph = nullptr;
         int off = -1, nslots = -1, tiles = -1, K = -1;
-        int variant = 0;
+        int variant = 0, tx = 0;
     };
     std::vector<Chunk> chunks;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -227,7 +227,8 @@ struct GpuBackend : Backend {
         const std::vector<int> first = cgi::cache_groups(bytes, kind, cgi::kPairBudget / 2, 2);
         const int ng = (int)first.size() - 1;
         std::vector<int> gtiles(ng, 0);
-        std::vector<int> gvar(ng, 0);      // the group's step-kernel variant
+        std::vector<int> gvar(ng, 0);      // the group's step-kernel variant (KV_XCH included)
+        std::vector<int> gtx(ng, 0);       // its threads per workgroup
         std::vector<long long> gnodes(ng, 0);
         for (int g = 0; g < ng; ++g)
             for (int i = first[g]; i < first[g + 1]; ++i) gnodes[g] += act[i]->nodes();
@@ -240,18 +241,27 @@ struct GpuBackend : Backend {
         }
         for (int g = 0; g < ng; ++g) {
             long long tiles = 0;
+            size_t gbytes = 0;
+            std::vector<lbm_ctx *> gctx;
+            for (int i = first[g]; i < first[g + 1]; ++i) {
+                gbytes += bytes[i];
+                gctx.push_back(act[i]->ctx);
+            }
+            const cgi::GroupPlan gp = cgi::plan_group(gbytes, storage, kind[first[g]], tx, gctx.data(), (int)gctx.size());
+            gvar[g] = gp.variant;
+            gtx[g] = gp.tx;
+            const bool xch = gp.variant & cgd::KV_XCH;
             for (int i = first[g]; i < first[g + 1]; ++i) {
                 const Request *r = act[i];
                 lbm_ctx *c = r->ctx;
                 cgd::SlotDesc d = c->desc;
-                cgi::set_geometry(d, &c->p, c->lay, tx, 1);
-                cgi::set_geometry(d, &c->p, c->lay, tx,
-                                  cgi::plan_strip(pair_nodes, c->p.ny, d.tiles_x, c->p.storage, 0, ng > 1));
+                cgi::set_geometry(d, &c->p, c->lay, gp.tx, 1, xch);
+                cgi::set_geometry(d, &c->p, c->lay, gp.tx,
+                                  cgi::plan_strip(pair_nodes, c->p.ny, d.tiles_x, c->p.storage, 0, ng > 1, xch), xch);
                 d.tile_begin = (int)tiles;
                 d.active_steps = (int)std::min<int64_t>(K, r->steps - r->done);
                 if (c->steps & 1) std::swap(d.buf[0], d.buf[1]);   // launch 0 reads the current buffer
                 tiles += (long long)d.tiles_x * d.tiles_y;
-                gvar[g] = cgd::step_variant(d);
                 table.push_back(d);
             }
             if (tiles > INT_MAX / 2) {
@@ -272,20 +282,20 @@ struct GpuBackend : Backend {
         for (int g = 0; g < ng && e == hipSuccess; ++g) {
             Chunk &ch = chunks[g];
             const int off = first[g], ns = first[g + 1] - first[g], nt = gtiles[g];
-            const int var = gvar[g];
-            if (ch.off != off || ch.nslots != ns || ch.tiles != nt || ch.K != K || ch.variant != var) {
+            const int var = gvar[g], gt = gtx[g];
+            if (ch.off != off || ch.nslots != ns || ch.tiles != nt || ch.K != K || ch.variant != var || ch.tx != gt) {
                 if (ch.graph) (void)hipGraphExecDestroy(ch.graph);
                 ch = Chunk{};
                 hipGraph_t gr = nullptr;
                 e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
                 hipError_t le = hipSuccess;
                 for (int j = 0; j < K && e == hipSuccess && le == hipSuccess; ++j)
-                    le = cgd::launch_step(storage, tx, d_slots + off, ns, nt, j & 1, j, cap, var);
+                    le = cgd::launch_step(storage, gt, d_slots + off, ns, nt, j & 1, j, cap, var);
                 if (e == hipSuccess) e = hipStreamEndCapture(cap, &gr);
                 if (e == hipSuccess) e = le;
                 if (e == hipSuccess) e = hipGraphInstantiate(&ch.graph, gr, nullptr, nullptr, 0);
                 if (gr) (void)hipGraphDestroy(gr);
-                if (e == hipSuccess) ch = Chunk{ch.graph, off, ns, nt, K, var};
+                if (e == hipSuccess) ch = Chunk{ch.graph, off, ns, nt, K, var, gt};
                 else ch = Chunk{};
             }
             if (e == hipSuccess) e = hipGraphLaunch(ch.graph, ng > 1 ? lane[glane[g]] : stream);
@@ -539,7 +549,7 @@ int lbm_server_create(size_t hbm_budget, int32_t max_slots, int32_t chunk_steps,
         return sfail(nullptr, LBM_E_INVAL, "tile_x must be 0, 64, 128 or 256");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return sfail(nullptr, LBM_E_DEVICE, "no HIP device");
-    auto be = std::make_unique<GpuBackend>(storage, tile_x ? tile_x : 64, max_slots);
+    auto be = std::make_unique<GpuBackend>(storage, tile_x, max_slots);   // tile_x 0: planned per group
     std::string e;
     if ((rc = be->setup(hip_stream, e)) != LBM_OK) return sfail(nullptr, rc, e);
     return create_server(std::move(be), hbm_budget, max_slots, chunk_steps, storage, out);

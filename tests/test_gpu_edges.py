@@ -1,7 +1,9 @@
 """Edge cases of the GPU step against the FP64 oracle: degenerate lattice
-sizes (one node, one row, one column), widths around the 60-column
-wavefront tile and the workgroup span, walls on one- and two-row channels,
-a two-column open channel, one fluid only, no surface tension, recolouring
+sizes (one node, one row, one column), widths around the 64-column
+wavefront block and the workgroup span, walls on one- and two-row channels,
+open channels from two columns wide to widths around a block (the outlet
+column then one of the halo nodes of the block next to it), one fluid
+only, no surface tension, recolouring
 strength beta at both ends of its range, and zero steps.  Bound: the FP32
 bound of the static bubble (max |d rho| / rho <= 1e-5, max |d u| <= 1e-6);
 the rough random fields of the size cases are compared population by
@@ -69,7 +71,9 @@ def _bounds(p, rr, rb, ux, uy, steps=STEPS):
 SIZES = [(1, 1, "periodic"), (1, 9, "periodic"), (9, 1, "periodic"), (2, 2, "periodic"), (5, 1, "walls"),
          (5, 2, "walls"), (1, 6, "walls"), (59, 7, "periodic"), (60, 7, "periodic"), (61, 7, "walls"),
          (119, 5, "periodic"), (121, 5, "walls"), (241, 3, "periodic"), (300, 1, "walls"),
-         (1, 4, "freeslip"), (7, 1, "freeslip"), (61, 2, "slip_top"), (125, 6, "freeslip")]
+         (1, 4, "freeslip"), (7, 1, "freeslip"), (61, 2, "slip_top"), (125, 6, "freeslip"),
+         (63, 5, "walls"), (64, 5, "periodic"), (65, 4, "freeslip"), (127, 3, "periodic"), (128, 3, "walls"),
+         (129, 4, "slip_top"), (130, 2, "walls"), (257, 3, "periodic")]
 
 
 @pytest.mark.parametrize("nx,ny,bcy", SIZES)
@@ -90,7 +94,7 @@ def test_degenerate_and_ragged_sizes(nx, ny, bcy):
     o.step(1)
     ref = o.get_pops()
     tol = None
-    for launch in ((64, 0), (256, 1)):
+    for launch in ((64, 0), (256, 1), (1024, 2)):
         with capi.Lattice(p) as g:
             g.set_launch(*launch)
             g.set_pops(state)
@@ -106,15 +110,17 @@ def test_degenerate_and_ragged_sizes(nx, ny, bcy):
         assert drho <= t_rho and du <= t_u
 
 
-def test_two_column_open_channel():
-    p = W.params(nx=2, ny=6, bc_x="open", bc_y="walls", rho0_r=1.0, rho0_b=2.0, tau_r=0.8, tau_b=0.9, A=1e-3,
+@pytest.mark.parametrize("nx", [2, 63, 64, 65, 66, 129])
+def test_narrow_open_channel(nx):
+    p = W.params(nx=nx, ny=6, bc_x="open", bc_y="walls", rho0_r=1.0, rho0_b=2.0, tau_r=0.8, tau_b=0.9, A=1e-3,
                  u_in_r=0.01, u_in_b=0.01, p_out=0.48)
     color = np.array([1, 1, 1, -1, -1, -1], dtype=np.int8)
-    rr = np.where(color[:, None] > 0, 1.0, 0.0) * np.ones((1, 2))
-    rb = np.where(color[:, None] > 0, 0.0, 2.0) * np.ones((1, 2))
-    drho, du = _errors(*_run(p, rr, rb, color=color))
-    say(f"open 2x6: drho/rho {drho:.2e} du {du:.2e}")
-    assert drho <= 1e-5 and du <= 1e-6
+    rr = np.where(color[:, None] > 0, 1.0, 0.0) * np.ones((1, nx))
+    rb = np.where(color[:, None] > 0, 0.0, 2.0) * np.ones((1, nx))
+    for launch in ((64, 0), (1024, 1)):
+        drho, du = _errors(*_run(p, rr, rb, color=color, launch=launch))
+        say(f"open {nx}x6 tile {launch[0]}: drho/rho {drho:.2e} du {du:.2e}")
+        assert drho <= 1e-5 and du <= 1e-6
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])

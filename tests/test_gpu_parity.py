@@ -240,23 +240,51 @@ def test_parity_open_channel_switching():
     assert du <= 1e-6
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
-def test_launch_shape_independence(storage):
-    """Tile width and strip height change only who computes a node, not what."""
-    p = W.params(nx=300, ny=45, bc_y="walls", rho0_r=1.0, rho0_b=4.0, tau_r=0.7, tau_b=0.9, A=1e-3,
-                 gx=1e-6, storage=storage)
-    rr, rb, ux, uy = W.random_fields(300, 45, seed=3, rho0_r=1.0, rho0_b=4.0)
+# (threads per workgroup, strip rows, step flavour: True block exchange,
+# False halo lanes, None planned)
+LAUNCH_SHAPES = ((256, 0, None), (64, 1, False), (128, 7, False), (64, 45, False), (256, 3, False),
+                 (64, 1, True), (128, 7, True), (256, 3, True), (512, 5, True), (1024, 2, True), (1024, 16, True))
+
+
+def _launch_shapes_agree(p, rr, rb, ux, uy, steps=50, color=None):
     ref = None
-    for tx, strip in ((256, 0), (64, 1), (128, 7), (64, 45), (256, 3)):
+    for tx, strip, xch in LAUNCH_SHAPES:
         with capi.Lattice(p) as g:
-            g.set_launch(tx, strip)
+            g.set_launch(tx, strip, exchange=xch)
             g.init(rr, rb, ux, uy)
-            g.step(50)
+            if color is not None:
+                g.set_inlet_color(color)
+            g.step(steps)
             pops = g.get_pops()
         if ref is None:
             ref = pops
         else:
-            assert np.array_equal(pops, ref), (tx, strip)
+            assert np.array_equal(pops, ref), (tx, strip, xch)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_launch_shape_independence(storage):
+    """Workgroup width, strip height and step flavour change only who computes
+    a node, not what: halo lanes, or whole blocks per wavefront with one
+    wavefront gathering its own halo nodes or several exchanging their edge
+    columns through LDS; strips of one row to the whole height."""
+    p = W.params(nx=300, ny=45, bc_y="walls", rho0_r=1.0, rho0_b=4.0, tau_r=0.7, tau_b=0.9, A=1e-3,
+                 gx=1e-6, storage=storage)
+    rr, rb, ux, uy = W.random_fields(300, 45, seed=3, rho0_r=1.0, rho0_b=4.0)
+    _launch_shapes_agree(p, rr, rb, ux, uy)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_launch_shape_independence_corrected_open(storage):
+    """The same with MRT and the Navier-Stokes correction (Q exchanged beside
+    the colour field) on an open channel with free-slip walls, whose outlet
+    column is a halo node of the block before it (130 = 2 x 64 + 2)."""
+    p = W.params(nx=130, ny=37, bc_x="open", bc_y="freeslip", collision="mrt", ns_correction=True,
+                 rho0_r=5.0, rho0_b=1.0, tau_r=0.7, tau_b=0.9, A=1e-3, u_in_r=0.01, u_in_b=0.01, p_out=0.48,
+                 storage=storage)
+    rr, rb, _, _ = W.random_fields(130, 37, seed=8, rho0_r=5.0, rho0_b=1.0)
+    color = np.where(np.arange(37) < 20, 1, -1).astype(np.int8)
+    _launch_shapes_agree(p, rr, rb, None, None, color=color)
 
 
 def test_graph_replay_matches_launches():
