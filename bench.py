@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the colour-gradient D2Q9 step on one MI355X.
 
-Default workload: the static-bubble sweep -- nine 512 x 512 periodic lattices
-(density ratio gamma in {10, 100, 1000} x dynamic-viscosity ratio M in
-{1, 10, 100}, seeded radii 64..128, sigma = 4.444e-4, beta = 0.7, FP32), all
-advanced by one batched kernel launch per time step.  A "step" is one time
-step of all nine lattices.  Inputs are synthetic and seeded; populations are
+Default workload: the inlet/outlet channel, 8192 x 512 nodes in FP32 -- the
+largest single-GPU configuration and the one whose populations (604 MB, both
+buffers) live in HBM rather than in the 256 MB Infinity Cache: a velocity
+inlet, a pressure outlet and free-slip walls, heavy liquid below light gas
+(density ratio 5, mu_g = mu_l / 2) entering at u = 0.01 with volume fractions
+0.8 / 0.2 (the paper's open-channel set-up of Sec. 5.2; its density-ratio-100
+alternating-injection recipe goes non-finite in the FP64 oracle within a few
+hundred steps, see the design notes).  A "step" is one time step of the
+lattice, one kernel launch.  Inputs are synthetic and seeded; populations are
 resident in HBM before the timed region starts.
 
-Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
-(algorithmic bytes 144 B per lattice update in FP32 -- 18 populations read and
-written -- or 80 B with 16-bit storage, where the 16 moving populations take
-2 B and the two rest populations 4 B, against 8 TB/s), the FP64 CPU oracle
-timed on a bounded sample on the host cores, and per-lattice diagnostics.
+Prints ONE JSON line: MLUPS, the roofline of the step kernel (algorithmic
+bytes 144 B per lattice update in FP32 -- 18 populations read and written --
+or 80 B with 16-bit storage, where the 16 moving populations take 2 B and the
+two rest populations 4 B, against 8 TB/s), the FP64 CPU oracle timed on a
+bounded sample on the host cores, the cache-resident nine-lattice sweep as a
+secondary figure, a plain copy's rate for context, and the storage-precision
+report of a converged bubble against the FP64 oracle.
 """
 import argparse
 import hashlib
@@ -47,6 +53,10 @@ def bytes_per_update(storage):
 
 
 def build_cells(args, W):
+    if args.workload == "channel":
+        c = W.inlet_outlet(seed=args.seed, storage=args.storage, collision=args.collision)
+        return [c], ("inlet/outlet channel 8192x512 (Sec. 5.2 open channel: velocity inlet, pressure outlet, "
+                     "free-slip walls, stratified inflow, density ratio 5)")
     if args.workload == "sweep512":
         return W.bubble_sweep(seed=args.seed, n=512, storage=args.storage, collision=args.collision), \
             "static-bubble sweep 512x512 x 9 cells (gamma x M)"
@@ -55,42 +65,110 @@ def build_cells(args, W):
     if args.workload == "slug":
         c = W.gravity_slug(seed=args.seed, gamma=10, Re=10, storage=args.storage, collision=args.collision)
         return [c], "gravity slug 4096x256"
-    if args.workload == "channel":
-        c = W.inlet_outlet(seed=args.seed, storage=args.storage, collision=args.collision)
-        return [c], "inlet/outlet channel 8192x512 (stratified inflow, density ratio 5)"
     if args.workload == "hbm8192":
         c = W.static_bubble(n=8192, radius=2048.0, storage=args.storage, collision=args.collision)
         return [c], "static bubble 8192x8192"
     raise SystemExit(f"unknown workload {args.workload}")
 
 
-def laplace(lat, cell):
-    """Laplace-law error of a bubble cell from FP64 device reductions."""
-    d0 = lat.diag(check=False)
-    if d0["n_nonfinite"] > 0:
-        return dict(stable=False, n_nonfinite=d0["n_nonfinite"])
-    R = math.sqrt(d0["area_r"] / math.pi)
-    cx, cy = cell["center"]
-    d = lat.diag(circle=(cx, cy, R - 4.0, R + 4.0), check=False)
-    p = cell["params"]
-    if p["sigma"] > 0:
-        sigma = p["sigma"]
-    else:
-        sigma = 4.0 * p["A"] / (9.0 * (1.0 / p["tau_r"]))
-    dp = d["p_in"] - d["p_out"]
-    return dict(stable=True, R=R, dp=dp, dp_theory=sigma / R, laplace_err=abs(dp / (sigma / R) - 1.0),
-                max_u=d["max_u"], mass_r=d["mass_r"], mass_b=d["mass_b"])
+def measure(capi, torch, stream, cells, steps, warmup, tile, strip):
+    """Time `steps` batched steps of the lattices of `cells` after `warmup`
+    untimed ones, with HIP events on the batch's stream."""
+    import numpy as np
+    sid = stream.cuda_stream
+    lats = []
+    for c in cells:
+        lat = capi.Lattice(c["params"], stream=sid)
+        if strip or tile:
+            lat.set_launch(tile, strip)
+        lat.init(c["rho_r"], c["rho_b"], c["ux"], c["uy"])
+        if "inlet_color" in c:
+            lat.set_inlet_color(c["inlet_color"])
+        elif "schedule" in c:
+            lat.set_inlet_color(np.full(c["params"]["ny"], c["schedule"][0][1], dtype=np.int8))
+        lats.append(lat)
+    batch = capi.Batch(lats, tile_x=tile, stream=sid)
+    launches = batch.groups
+    plans = [batch.group_launch(g) for g in range(launches)]
+    nodes = sum(c["params"]["nx"] * c["params"]["ny"] for c in cells)
+    nbytes = sum(2 * lat.buffer_bytes for lat in lats)
+    batch.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    batch.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    state = []
+    for lat in lats:
+        d = lat.diag(check=False)
+        state.append(dict(n_nonfinite=d["n_nonfinite"], max_u=d["max_u"]))
+    batch.close()
+    for lat in lats:
+        lat.close()
+    flav = sorted({"block exchange" if x else "halo lanes" for _, x in plans})
+    launch = (f"k_step, {launches} launches per step ({', '.join(flav)}; groups of lattices sized for the Infinity "
+              f"Cache, two in flight on two streams), HIP-graph replay of 32 steps" if launches > 1 else
+              f"k_step ({flav[0]}, {plans[0][0]} threads per workgroup), one launch per step, HIP-graph replay "
+              f"of 32 steps")
+    return dict(mlups=nodes * steps / (ms / 1e3) / 1e6, ms_per_step=ms / max(steps, 1), launches=launches,
+                nodes=nodes, bytes=nbytes, wall=wall, state=state, flavour=", ".join(flav), launch=launch)
 
 
-def cpu_baseline(cell, seconds):
+def copy_rate(capi, W, torch, stream, gib):
+    """A plain device copy of `gib` GiB (the library's copy kernel): the
+    achievable bandwidth beside the 8 TB/s spec, and the calibration of the
+    traffic counters."""
+    n = int(gib * (1 << 30))
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    probe = capi.Lattice(W.params(nx=64, ny=64, A=1e-3), stream=stream.cuda_stream)
+    for _ in range(3):
+        probe.bw_copy(b.data_ptr(), a.data_ptr(), n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        probe.bw_copy(b.data_ptr(), a.data_ptr(), n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    probe.close()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_bytes": n, "copy_ms": ms, "copy_gbs": 2 * n / ms / 1e6}
+
+
+def stored_counters(args):
+    """HBM bytes per launch and VALU instructions per lattice update from the
+    rocprofv3 counter runs summarised under profiles/, while the kernel
+    sources are the ones those runs measured (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, None
+    try:
+        tr = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None, None
+    if tr.get("kernel_hash") != kernel_hash():
+        return None, None
+    key = (f"{args.workload}/{args.storage}/{args.collision}" + ("/nsc" if args.ns_correction else "")
+           + ("/iso" if args.gradient == "isotropic" else ""))
+    return tr.get("per_launch", {}).get(key), tr.get("valu_per_update", {}).get(key)
+
+
+def cpu_baseline(cell, seconds, steps_cap=2000):
     """The FP64 oracle on one lattice of the workload, on the host cores."""
     import oracle
     p = dict(cell["params"])
     s = oracle.Sim(**p).init(cell["rho_r"], cell["rho_b"], cell["ux"], cell["uy"])
+    if "inlet_color" in cell:
+        s.set_inlet_color(cell["inlet_color"])
     t0 = time.perf_counter()
     s.step(1)
     t1 = time.perf_counter() - t0
-    steps = max(1, min(2000, int(seconds / max(t1, 1e-6))))
+    steps = max(1, min(steps_cap, int(seconds / max(t1, 1e-6))))
     t0 = time.perf_counter()
     s.step(steps)
     dt = time.perf_counter() - t0
@@ -353,9 +431,10 @@ def main_serve(args, log):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="sweep512")
+    ap.add_argument("--workload", default="channel",
+                    help="channel (default), sweep512, slug, hbm8192, bubble64 or serve")
     ap.add_argument("--storage", default=None, choices=["f32", "f16s", "bf16s"],
                     help="population storage (default f32; f16s for the serving mix)")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
@@ -370,6 +449,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the storage-precision report (converged 64x64 bubble vs the FP64 oracle)")
+    ap.add_argument("--cpu-steps", type=int, default=2000, help="at most this many oracle steps in cpu_baseline")
+    ap.add_argument("--no-secondary", action="store_true", help="channel: skip the cache-resident sweep figure")
+    ap.add_argument("--secondary-steps", type=int, default=2000, help="steps of the cache-resident sweep figure")
+    ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy bandwidth figure")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--load", type=float, default=0.8, help="serve: offered load / measured capacity")
     ap.add_argument("--chunk", type=int, default=100, help="serve: steps per chunk")
@@ -396,7 +479,6 @@ def main():
         main_serve(args, log)
         return
 
-    import numpy as np
     import torch
     from paper_1903_01168_amd import capi
     from paper_1903_01168_amd import workloads as W
@@ -407,22 +489,7 @@ def main():
     sid = stream.cuda_stream
 
     if args.copy_only > 0:
-        n = int(args.copy_only * (1 << 30))
-        a = torch.empty(n, dtype=torch.uint8, device="cuda")
-        b = torch.empty(n, dtype=torch.uint8, device="cuda")
-        probe = capi.Lattice(W.params(nx=64, ny=64, A=1e-3), stream=sid)
-        for _ in range(3):
-            probe.bw_copy(b.data_ptr(), a.data_ptr(), n)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record(stream)
-        for _ in range(reps):
-            probe.bw_copy(b.data_ptr(), a.data_ptr(), n)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        print(json.dumps({"copy_bytes": n, "copy_ms": ms, "copy_gbs": 2 * n / ms / 1e6}))
+        print(json.dumps(copy_rate(capi, W, torch, stream, args.copy_only)))
         return
 
     cells, wname = build_cells(args, W)
@@ -433,101 +500,73 @@ def main():
             c["params"]["ns_correction"] = True
     for c in cells:
         c["params"]["gradient"] = args.gradient
-    lats = []
-    for c in cells:
-        lat = capi.Lattice(c["params"], stream=sid)
-        if args.strip or args.tile:
-            lat.set_launch(args.tile, args.strip)
-        lat.init(c["rho_r"], c["rho_b"], c["ux"], c["uy"])
-        if "inlet_color" in c:
-            lat.set_inlet_color(c["inlet_color"])
-        elif "schedule" in c:
-            lat.set_inlet_color(np.full(c["params"]["ny"], c["schedule"][0][1], dtype=np.int8))
-        lats.append(lat)
-    mass0 = [lat.diag(check=False) for lat in lats]
-    batch = capi.Batch(lats, tile_x=args.tile, stream=sid)
-    launches = batch.groups              # cache-sized groups: kernel launches per step
-    nodes = sum(c["params"]["nx"] * c["params"]["ny"] for c in cells)
-
-    batch.step(args.warmup)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    batch.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    ms_per_step = ms / max(args.steps, 1)
-    mlups = nodes * args.steps / (ms / 1e3) / 1e6
+    m = measure(capi, torch, stream, cells, args.steps, args.warmup, args.tile, args.strip)
+    log(f"{wname}: {m['mlups']:.0f} MLUPS, {m['ms_per_step'] * 1e3:.1f} us per step, "
+        f"{m['launches']} launch(es) per step")
 
     bpu = bytes_per_update(args.storage)
-    # algorithmic bytes of a step over the step's time: a step is `launches`
-    # launches (one per group of lattices), two of them in flight at a time
-    # when there are several, so the step's time is the union of the kernels'
-    # busy intervals
-    achieved = bpu * nodes / (ms_per_step / 1e3) / 1e9
-    # HBM bytes per launch and VALU instructions per lattice update, from the
-    # rocprofv3 counter runs summarised under profiles/ (only while the kernel
-    # sources are the ones those runs measured)
-    traffic, valu = None, None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            key = (f"{args.workload}/{args.storage}/{args.collision}" + ("/nsc" if args.ns_correction else "")
-                   + ("/iso" if args.gradient == "isotropic" else ""))
-            if tr.get("kernel_hash") == kernel_hash():
-                traffic = tr.get("per_launch", {}).get(key)
-                valu = tr.get("valu_per_update", {}).get(key)
-        except (OSError, ValueError):
-            traffic, valu = None, None
+    nodes = m["nodes"]
+    # algorithmic bytes of one launch over the launch's average duration:
+    # with one launch per step (a single lattice) the launches run back to
+    # back on one stream and the HIP events around the timed region give their
+    # average; with several launches per step (groups of a batch, two in
+    # flight on two streams) only the step's time is defined, and the figure
+    # is the algorithmic bytes of a step over it
+    achieved = bpu * nodes / (m["ms_per_step"] / 1e3) / 1e9
+    traffic, valu = stored_counters(args)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "bytes_per_update": bpu, "kernel": "k_step", "launches_per_step": launches,
-                "step_us": ms_per_step * 1e3, "kernel_hash": kernel_hash()}
-    if launches > 1:
-        roofline["note"] = ("two k_step launches in flight on two streams: achieved = algorithmic bytes of a step / "
-                            "step time (HIP events on the batch stream), i.e. over the union of the launches' "
-                            "busy intervals, not per launch")
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_update": bpu,
+                "kernel": "k_step", "flavour": m["flavour"], "launches_per_step": m["launches"],
+                "launch_us" if m["launches"] == 1 else "step_us": m["ms_per_step"] * 1e3,
+                "kernel_hash": kernel_hash(),
+                "definition": "achieved = bytes_per_update x lattice nodes of one launch / average launch "
+                              "duration (HIP events around the timed launches on their stream)"
+                              if m["launches"] == 1 else
+                              "achieved = bytes_per_update x nodes of one step / step time (several launches "
+                              "per step, two in flight on two streams)"}
+    if m["bytes"] <= 256 << 20:
+        roofline["note"] = ("working set within MI355X's 256 MB Infinity Cache: a cache rate, not an HBM "
+                            "figure")
     if valu is not None:
-        # VALU issue: one wave64 instruction per SIMD every 4 cycles, 1024 SIMDs
-        # at 2.4 GHz (unpacked); the 16-bit codec makes those kernels VALU-bound
-        v = dict(per_update=valu, achieved=mlups * 1e6 * valu / 1e9, peak=VALU_PEAK_GIPS,
+        v = dict(per_update=valu, achieved=m["mlups"] * 1e6 * valu / 1e9, peak=VALU_PEAK_GIPS,
                  unit="G wave64 VALU instructions/s")
         v["frac"] = v["achieved"] / VALU_PEAK_GIPS
         if args.storage == "f32":
             roofline["valu"] = v
         else:
+            # the 16-bit codec makes those kernels VALU-bound
             hbm = {k: roofline[k] for k in ("achieved", "peak", "unit", "frac")}
             roofline.update(bound="alu", achieved=v["achieved"], peak=v["peak"], unit=v["unit"], frac=v["frac"],
                             valu_per_update=valu, hbm=hbm)
 
-    cells_out = []
-    for lat, c, m0 in zip(lats, cells, mass0):
-        info = dict(name=c["name"])
-        if "center" in c:
-            info.update(laplace(lat, c))
-        d = lat.diag(check=False)
-        info["mass_drift_r"] = (d["mass_r"] - m0["mass_r"]) / m0["mass_r"] if m0["mass_r"] else 0.0
-        info["mass_drift_b"] = (d["mass_b"] - m0["mass_b"]) / m0["mass_b"] if m0["mass_b"] else 0.0
-        info["n_nonfinite"] = d["n_nonfinite"]
-        cells_out.append(info)
-
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cells[0], args.cpu_seconds)
+        cpu = cpu_baseline(cells[0], args.cpu_seconds, steps_cap=args.cpu_steps)
+    secondary = None
+    if args.workload == "channel" and not args.no_secondary:
+        # the cache-resident counterpart: the 9 x 512^2 static-bubble sweep
+        # (340 MB in groups sized for the Infinity Cache)
+        sw = W.bubble_sweep(seed=args.seed, n=512, storage=args.storage, collision=args.collision)
+        ms = measure(capi, torch, stream, sw, args.secondary_steps, 64, 0, 0)
+        secondary = {"workload": "static-bubble sweep 9 x 512^2 (gamma in {10,100,1000} x M in {1,10,100})",
+                     "value": ms["mlups"], "unit": "MLUPS", "ms_per_step": ms["ms_per_step"],
+                     "launches_per_step": ms["launches"], "steps": args.secondary_steps,
+                     "alg_gbs": bpu * ms["nodes"] / (ms["ms_per_step"] / 1e3) / 1e9,
+                     "note": "mall-resident: lattices stepped in groups that stay in the 256 MB Infinity Cache "
+                             "between steps; a cache rate, not an HBM figure"}
+        secondary["frac_of_hbm_peak"] = secondary["alg_gbs"] / HBM_PEAK_GBS
+    copy = None if args.no_copy else copy_rate(capi, W, torch, stream, 1.0)
     precision = None if args.no_precision else precision_report(sid)
 
     p0 = cells[0]["params"]
     out = {
         "metric": "MLUPS & HBM GB/s (% of peak), color-gradient D2Q9; p50/p99 solve latency",
-        "value": mlups,
+        "value": m["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -536,21 +575,17 @@ def main():
         "config": {"workload": wname, "lattices": len(cells), "nx": p0["nx"], "ny": p0["ny"],
                    "nodes": nodes, "storage": args.storage, "collision": args.collision,
                    "ns_correction": bool(args.ns_correction), "gradient": args.gradient,
-                   "steps_simulated": args.warmup + args.steps, "seed": args.seed,
-                   "launch": (f"batched k_step, {launches} launches per step: lattices in groups sized so that "
-                              "two fit the Infinity Cache together, two groups in flight on two streams (rounds "
-                              "of 256 steps per group), HIP-graph replay of 32 steps" if launches > 1 else
-                              "batched k_step, one launch per step, HIP-graph replay of 32 steps")},
+                   "population_bytes": m["bytes"], "steps_simulated": args.warmup + args.steps,
+                   "seed": args.seed, "launch": m["launch"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mall_resident": secondary,
+        "hbm_copy": copy,
         "precision": precision,
-        "wall_s": wall,
-        "cells": cells_out,
+        "wall_s": m["wall"],
+        "state": m["state"],
     }
-    print(json.dumps(out))
-    batch.close()
-    for lat in lats:
-        lat.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -222,8 +222,10 @@ void *lbm_stream(const lbm_ctx *ctx);
  * arithmetic is exactly that of lbm_step, so results are bit-identical to
  * stepping the contexts one by one, in any grouping.  The contexts must not
  * be stepped outside the batch while it exists (LBM_E_INVAL otherwise);
- * lbm_moments / lbm_diag / checkpoints on them stay valid.  tile_x: 0
- * (automatic), 64, 128 or 256. */
+ * lbm_moments / lbm_diag / checkpoints on them stay valid.  tile_x: threads
+ * per workgroup, 0 (planned per group), 64, 128, 256, 512 or 1024.  Each
+ * group's step flavour is planned (lbm_set_exchange: block exchange for FP32
+ * groups whose two buffers exceed 256 MiB). */
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_stream, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t n);
@@ -232,6 +234,11 @@ const char *lbm_batch_last_error(const lbm_batch *b);
 /* Number of cache-sized groups of the batch, i.e. kernel launches per step
  * (0 for a NULL batch). */
 int lbm_batch_groups(const lbm_batch *b);
+/* Launch shape of group g (0 <= g < lbm_batch_groups): threads per workgroup
+ * and step flavour (1: block exchange, 0: halo lanes; see lbm_set_exchange).
+ * Either pointer may be NULL.  Errors: LBM_E_INVAL for a NULL batch or a
+ * group out of range. */
+int lbm_batch_group_launch(const lbm_batch *b, int32_t g, int32_t *tile_x, int32_t *exchange);
 
 /* Plain device-to-device copy of n bytes on the context stream (measures
  * achievable HBM bandwidth beside the step). */

@@ -64,6 +64,7 @@ EXPORTS = [
     "lbm_steps_done", "lbm_sync", "lbm_moments", "lbm_diag", "lbm_get_pops", "lbm_set_pops",
     "lbm_save_state", "lbm_load_state", "lbm_set_launch", "lbm_set_exchange", "lbm_stream", "lbm_bw_copy",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_groups",
+    "lbm_batch_group_launch",
 ]
 
 _LIB = None
@@ -112,6 +113,7 @@ def load(path: str = LIB_PATH):
     L.lbm_batch_last_error.restype = C.c_char_p
     L.lbm_batch_last_error.argtypes = [_P]
     L.lbm_batch_groups.argtypes = [_P]
+    L.lbm_batch_group_launch.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     _LIB = L
     return L
 
@@ -288,6 +290,14 @@ class Batch:
     def groups(self) -> int:
         """Cache-sized groups, i.e. kernel launches per step."""
         return int(self.L.lbm_batch_groups(self._h))
+
+    def group_launch(self, g):
+        """(threads per workgroup, block-exchange flavour) of group g."""
+        tx, xch = C.c_int32(), C.c_int32()
+        rc = self.L.lbm_batch_group_launch(self._h, int(g), C.byref(tx), C.byref(xch))
+        if rc != LBM_OK:
+            raise LbmError(rc, self.L.lbm_last_error(None).decode())
+        return tx.value, bool(xch.value)
 
     def step(self, n=1):
         rc = self.L.lbm_batch_step(self._h, int(n))

@@ -973,6 +973,14 @@ static int group_steps(lbm_batch *b, BatchGroup &G, int64_t start, int64_t n, hi
 
 int lbm_batch_groups(const lbm_batch *b) { return b ? (int)b->groups.size() : 0; }
 
+int lbm_batch_group_launch(const lbm_batch *b, int32_t g, int32_t *tile_x, int32_t *exchange)
+{
+    if (!b || g < 0 || g >= (int)b->groups.size()) return fail(nullptr, LBM_E_INVAL, "no such group");
+    if (tile_x) *tile_x = b->groups[g].tx;
+    if (exchange) *exchange = (b->groups[g].variant & cgd::KV_XCH) ? 1 : 0;
+    return LBM_OK;
+}
+
 int lbm_batch_step(lbm_batch *b, int64_t n)
 {
     if (!b) return fail(nullptr, LBM_E_INVAL, "batch is NULL");
