@@ -177,6 +177,18 @@ int lbm_moments(lbm_ctx *ctx, double *rho_r, double *rho_b, double *ux, double *
  * circle (nullable) = {cx, cy, r_in, r_out}: the mean pressure is taken over
  * nodes whose cell centre (x+1/2, y+1/2) lies at r < r_in and r > r_out. */
 int lbm_diag(lbm_ctx *ctx, const double *circle, lbm_diag_t *d);
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid it): lbm_diag with
+ * its reduction scratch -- per-block FP64 partial sums and the final sums --
+ * in a fixed per-device array of the library (147 528 bytes, 2048 blocks of
+ * partials, held by each GPU the library runs on until the process ends)
+ * instead of the context's work buffers.  Same kernels, same block count and
+ * order, so the same bits as lbm_diag.  Allocates nothing; copies the nine
+ * sums to the host and synchronises the context's stream.  All calls on one
+ * GPU share that array: calls that overlap on one GPU (several threads or
+ * streams) race.  Errors: as lbm_diag; LBM_E_INVAL if the lattice needs more
+ * reduction blocks than the array holds (never, with the current block cap). */
+int lbm_diag_noalloc(lbm_ctx *ctx, const double *circle, lbm_diag_t *d);
 
 /* Populations of the stored state, decoded to FP64, layout [2][9][ny][nx]
  * (colour, direction, y, x); and the reverse (encoded to the storage type). */

@@ -61,7 +61,7 @@ class LbmDiag(C.Structure):
 EXPORTS = [
     "lbm_version", "lbm_last_error", "lbm_bytes_required", "lbm_buffer_bytes", "lbm_create",
     "lbm_create_ext", "lbm_destroy", "lbm_init_fields", "lbm_set_inlet_color", "lbm_step",
-    "lbm_steps_done", "lbm_sync", "lbm_moments", "lbm_diag", "lbm_get_pops", "lbm_set_pops",
+    "lbm_steps_done", "lbm_sync", "lbm_moments", "lbm_diag", "lbm_diag_noalloc", "lbm_get_pops", "lbm_set_pops",
     "lbm_save_state", "lbm_load_state", "lbm_set_launch", "lbm_set_exchange", "lbm_stream", "lbm_bw_copy",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_groups",
     "lbm_batch_group_launch",
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     L.lbm_sync.argtypes = [_P]
     L.lbm_moments.argtypes = [_P, _D, _D, _D, _D, _D, C.POINTER(LbmDiag)]
     L.lbm_diag.argtypes = [_P, _D, C.POINTER(LbmDiag)]
+    L.lbm_diag_noalloc.argtypes = [_P, _D, C.POINTER(LbmDiag)]
     L.lbm_get_pops.argtypes = [_P, _D]
     L.lbm_set_pops.argtypes = [_P, _D]
     L.lbm_save_state.argtypes = [_P, _P, C.c_size_t, C.POINTER(C.c_size_t)]

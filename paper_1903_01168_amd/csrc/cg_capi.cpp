@@ -647,6 +647,29 @@ int lbm_diag(lbm_ctx *c, const double *circle, lbm_diag_t *d)
     return LBM_OK;
 }
 
+int lbm_diag_noalloc(lbm_ctx *c, const double *circle, lbm_diag_t *d)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!d) return fail(c, LBM_E_INVAL, "d is NULL");
+    DeviceGuard g(c->device);
+    const long long n = (long long)c->p.nx * c->p.ny;
+    const int nb = cgd::moments_blocks(n);
+    if (nb > cgd::kMaxMomentBlocks)
+        return fail(c, LBM_E_INVAL, "lattice needs more reduction blocks than the no-alloc scratch holds");
+    double *scr = nullptr;
+    hipError_t e = cgd::scratch_device_ptr(&scr);
+    if (e != hipSuccess) return hip_fail(c, e, "no-alloc scratch address");
+    double *out = scr + (size_t)nb * 9;
+    double o[9];
+    e = cgd::launch_moments(c->p.storage, c->d_desc, n, (int)(c->steps & 1), nullptr, scr, out, circle, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(o, out, sizeof o, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diag (no-alloc)");
+    to_diag(c, o, d);
+    if (o[7] > 0) return fail(c, LBM_E_UNSTABLE, "non-finite values in the lattice");
+    return LBM_OK;
+}
+
 static int pops_io(lbm_ctx *c, double *out, const double *in)
 {
     DeviceGuard g(c->device);

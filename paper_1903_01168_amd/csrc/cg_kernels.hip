@@ -11,6 +11,8 @@
 //  k_reduce    fixed-order FP64 reduction of the per-block partials.
 //  k_get/set   decode / encode the stored populations to a plain FP32 layout.
 //  k_copy      plain streaming copy (achievable-bandwidth reference).
+#include <mutex>
+
 #include "cg_kernels.hpp"
 
 namespace cgd {
@@ -990,6 +992,36 @@ hipError_t launch_init(int storage, const SlotDesc *d, long long nodes, const fl
 }
 
 int moments_blocks(long long nodes) { return grid_for(nodes); }
+
+// ------------------------------------------------------ no-alloc scratch --
+// The diagnostics reduction's scratch for callers that cannot allocate
+// (lbm_diag_noalloc): per-block FP64 partial sums of up to 2048 blocks (the
+// most launch_moments uses) and the final nine sums, 147 528 bytes.  Each GPU
+// holds its own copy for the life of the process; host code uses its device
+// address from hipGetSymbolAddress, never the array's name.  Every block
+// writes its partials and k_reduce the sums, so nothing needs clearing; calls
+// that overlap on one GPU share it and race.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_device_ptr(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // with device `dev` current
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double *>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_moments(int storage, const SlotDesc *d, long long nodes, int parity, float *fields,
                           double *partial, double *out, const double *circle, hipStream_t s)

@@ -24,6 +24,12 @@ hipError_t launch_step(int storage, int tx, const SlotDesc *d, int nslots, int t
 hipError_t launch_init(int storage, const SlotDesc *d, long long nodes, const float *fields, int which,
                        hipStream_t s);
 int moments_blocks(long long nodes);
+// Device scratch of lbm_diag_noalloc: room for the partial sums of
+// kMaxMomentBlocks blocks (9 each) and the nine final sums.
+constexpr int kMaxMomentBlocks = 2048;
+constexpr size_t kScratchDoubles = (size_t)kMaxMomentBlocks * 9 + 9;
+// Its address on the current device (looked up once per device).
+hipError_t scratch_device_ptr(double **out);
 hipError_t launch_moments(int storage, const SlotDesc *d, long long nodes, int parity, float *fields,
                           double *partial, double *out, const double *circle, hipStream_t s);
 hipError_t launch_pops(int storage, const SlotDesc *d, long long nodes, int which, float *buf, bool get,
