@@ -36,7 +36,12 @@ class OrParams(C.Structure):
         ("contact_angle", C.c_double),
         ("ns_correction", C.c_int),
         ("gradient", C.c_int),
+        ("alt", C.c_int),
     ]
+
+
+# or_params.alt: alternative readings of rules the paper leaves open
+ALT_Q_WALL_ZERO, ALT_ISO_EXTRAP, ALT_OUTLET_UPSTREAM = 1, 2, 4
 
 
 _D = C.POINTER(C.c_double)
@@ -59,6 +64,8 @@ def lib():
         L.or_moments.argtypes = [C.c_void_p, _D, _D, _D, _D, _D]
         L.or_get_pops.argtypes = [C.c_void_p, _D]
         L.or_set_pops.argtypes = [C.c_void_p, _D]
+        L.or_gradients.argtypes = [C.c_void_p, _D, _D, _D, _D]
+        L.or_round_f32.argtypes = [C.c_void_p]
         L.or_step_count.restype = C.c_long
         L.or_step_count.argtypes = [C.c_void_p]
         L.or_threads.restype = C.c_int
@@ -216,7 +223,7 @@ class Sim:
                  percolor=False, rho0_r=1.0, rho0_b=1.0, alpha_light=0.2, tau_r=1.0,
                  tau_b=1.0, delta=0.1, A=0.0, sigma=0.0, beta=0.7, mrt_lambda=0.8,
                  gx=0.0, gy=0.0, u_in_r=0.0, u_in_b=0.0, p_out=0.0, contact_angle=-1.0,
-                 ns_correction=False, gradient="nearest", **_ignored):
+                 ns_correction=False, gradient="nearest", alt=0, **_ignored):
         self.nx, self.ny = nx, ny
         by, slo, shi = self.BC_Y[bc_y]
         p = OrParams(nx=nx, ny=ny,
@@ -227,7 +234,7 @@ class Sim:
                      tau_r=tau_r, tau_b=tau_b, delta=delta, A=A, sigma=sigma, beta=beta,
                      mrt_lambda=mrt_lambda, gx=gx, gy=gy, u_in_r=u_in_r, u_in_b=u_in_b,
                      p_out=p_out, contact_angle=contact_angle, ns_correction=int(bool(ns_correction)),
-                     gradient={"nearest": 0, "isotropic": 1}[gradient])
+                     gradient={"nearest": 0, "isotropic": 1}[gradient], alt=int(alt))
         self._params = p
         self._h = lib().or_create(C.byref(p))
         if not self._h:
@@ -253,8 +260,15 @@ class Sim:
         assert c.shape == (self.ny,)
         lib().or_set_inlet_color(self._h, c.ctypes.data_as(C.POINTER(C.c_int8)))
 
-    def step(self, n=1):
-        lib().or_step(self._h, int(n))
+    def step(self, n=1, round_f32=False):
+        """n steps; round_f32: round the stored populations to FP32 after
+        each (a storage model for measuring how the flow amplifies rounding)."""
+        if not round_f32:
+            lib().or_step(self._h, int(n))
+            return self
+        for _ in range(int(n)):
+            lib().or_step(self._h, 1)
+            lib().or_round_f32(self._h)
         return self
 
     @property
@@ -277,3 +291,13 @@ class Sim:
     def set_pops(self, pops):
         a = _f64(pops).reshape(2, 9, self.ny, self.nx)
         lib().or_set_pops(self._h, _p(a))
+
+    def gradients(self):
+        """The colour gradient (before any contact-angle turn) and, with the
+        Navier-Stokes correction, dQx/dx and dQy/dy per colour, that the next
+        step would use; the state is not advanced."""
+        sh = (self.ny, self.nx)
+        Fx, Fy = np.zeros(sh), np.zeros(sh)
+        dqx, dqy = np.zeros((2,) + sh), np.zeros((2,) + sh)
+        lib().or_gradients(self._h, _p(Fx), _p(Fy), _p(dqx), _p(dqy))
+        return dict(Fx=Fx, Fy=Fy, dqxdx=dqx, dqydy=dqy)

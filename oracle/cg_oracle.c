@@ -32,7 +32,8 @@
  *  R7  open boundaries (Sec. 2.5): Zou-He formulas rotated to a west velocity
  *      inlet and an east pressure outlet; inlet colour prescribed per row;
  *      outlet colour = volume fraction of the six populations that stream in
- *      from the domain; outlet densities rho_k = chi_k p_out / c_s,k^2.
+ *      from the domain, clamped to [0, 1] as the (phi + 1) / 2 of a colour
+ *      field in [-1, 1]; outlet densities rho_k = chi_k p_out / c_s,k^2.
  *  R8  collision is colour-blind (same omega_eff and S for both colours); the
  *      percolor switch runs the per-colour form for comparison.
  *  R6b free slip (Sec. 2.5 item 1): a diagonal population that would come
@@ -47,15 +48,19 @@
  *      (printed with a factor 3, omega_eff and a plus sign).
  *  R14 Q^k = (1.8 alpha_k - 0.8) rho_k u with the half-force velocity; its
  *      ghost values beyond walls and open faces follow the colour field's
- *      rules (R6): parity unpinned (the paper gives no rule; pinned are the
- *      periodic decay rates).  Zou-He H uses the prescribed (inlet) or
+ *      rules (R6) (the paper gives no rule).  Zou-He H uses the prescribed (inlet) or
  *      measured (outlet) colour fractions of R7.
  *  R15 the more isotropic gradient the paper mentions (Sec. 4) as an option:
  *      the 25-point second-neighbour stencil isotropic to 8th order.  Its
  *      outer ghost cells: beyond an open face the nearest column (R6);
  *      beyond a wall the inner ghost row (Sec. 2.4 defines solid nodes with
  *      fluid neighbours only); corner cells beyond both take the inner ghost
- *      column of the ghost row.  The boundary rule is parity unpinned.
+ *      column of the ghost row.
+ *  R6, R14 and R15's ghost values are pinned by closed-form gradients of
+ *  fields that vary along the wall; where the paper leaves a rule open (R7's
+ *  outlet colour, R14's Q beyond a wall, R15's outer ghost row) the
+ *  alternative reading is selectable (or_params.alt) so that its effect can
+ *  be measured.
  */
 #include "cg_oracle.h"
 
@@ -570,7 +575,15 @@ static void pass_densities_and_open_bc(or_sim *s)
             for (int k = 0; k < 2; ++k)
                 for (int j = 0; j < 6; ++j) kn[k] += POP(s->strm, k, known[j], y, x);
             double vol_r = kn[0] / s->rho0[0], vol_b = kn[1] / s->rho0[1];
+            if (s->p.alt & OR_ALT_OUTLET_UPSTREAM) {
+                /* the colour of the node upstream, at this step */
+                vol_r = s->rho[(size_t)y * nx + (nx - 2)] / s->rho0[0];
+                vol_b = s->rho[n + (size_t)y * nx + (nx - 2)] / s->rho0[1];
+            }
             double chi[2] = {vol_r / (vol_r + vol_b), vol_b / (vol_r + vol_b)};
+            /* a colour fraction, (phi + 1) / 2 with phi in [-1, 1]: a trace
+             * colour whose incoming populations sum below zero has none */
+            for (int k = 0; k < 2; ++k) chi[k] = chi[k] < 0.0 ? 0.0 : (chi[k] > 1.0 ? 1.0 : chi[k]);
             double rk[2] = {chi[0] * s->p.p_out / s->cs2[0], chi[1] * s->p.p_out / s->cs2[1]};
             for (int i = 0; i < 9; ++i) N[i] = POP(s->strm, 0, i, y, x) + POP(s->strm, 1, i, y, x);
             double kap = s->p.ns_correction ? chi[0] * (3.0 * s->cs2[0] - 1.0) + chi[1] * (3.0 * s->cs2[1] - 1.0)
@@ -660,6 +673,9 @@ static void fill_ghosts(const or_sim *s, double *f)
         if (s->p.bc_y == OR_BCY_PERIODIC) {
             f[gidx(s, x, -2)] = f[gidx(s, x, wrap(-2, ny))];
             f[gidx(s, x, ny + 1)] = f[gidx(s, x, wrap(ny + 1, ny))];
+        } else if (s->p.alt & OR_ALT_ISO_EXTRAP) {
+            f[gidx(s, x, -2)] = 2.0 * f[gidx(s, x, -1)] - f[gidx(s, x, 0)];
+            f[gidx(s, x, ny + 1)] = 2.0 * f[gidx(s, x, ny)] - f[gidx(s, x, ny - 1)];
         } else {
             f[gidx(s, x, -2)] = f[gidx(s, x, -1)];
             f[gidx(s, x, ny + 1)] = f[gidx(s, x, ny)];
@@ -692,6 +708,12 @@ static void pass_color_field(or_sim *s)
             }
         fill_ghosts(s, qx);
         fill_ghosts(s, qy);
+        if ((s->p.alt & OR_ALT_Q_WALL_ZERO) && s->p.bc_y == OR_BCY_WALLS)
+            for (int x = -GW; x < nx + GW; ++x)
+                for (int gy = 1; gy <= GW; ++gy) {
+                    qx[gidx(s, x, -gy)] = qy[gidx(s, x, -gy)] = 0.0;
+                    qx[gidx(s, x, ny - 1 + gy)] = qy[gidx(s, x, ny - 1 + gy)] = 0.0;
+                }
     }
 }
 
@@ -713,6 +735,23 @@ static void q_divergence(const or_sim *s, int k, int x, int y, double *dqx, doub
     *dqy = Gy[1];
 }
 
+/* colour gradient at (x, y) from the extended psi field: eq. (colorGradient),
+ * or the second-neighbour isotropic stencil (R15); before any wetting turn */
+static void node_gradient(const or_sim *s, int x, int y, double *F)
+{
+    double patch[25];
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) patch[(dy + 2) * 5 + (dx + 2)] = s->psi[gidx(s, x + dx, y + dy)];
+    if (s->p.gradient == 1) {
+        or_gradient5x5(patch, F);
+    } else {
+        double p9[9];
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) p9[(dy + 1) * 3 + (dx + 1)] = patch[(dy + 2) * 5 + (dx + 2)];
+        or_gradient3x3(p9, F);
+    }
+}
+
 /* Pass 5: per node collision (Sec. 2.1), perturbation (Sec. 2.2),
  * recolouring (Sec. 2.3); result into the post-recolouring state. */
 static void pass_collide(or_sim *s)
@@ -726,20 +765,8 @@ static void pass_collide(or_sim *s)
             size_t c = (size_t)y * nx + x;
             double rk[2] = {s->rho[c], s->rho[n + c]};
             double u = s->ux[c], v = s->uy[c];
-            /* colour gradient from the extended psi field: eq. (colorGradient),
-               or the second-neighbour isotropic stencil (R15) */
-            double patch[25], F[2];
-            for (int dy = -2; dy <= 2; ++dy)
-                for (int dx = -2; dx <= 2; ++dx)
-                    patch[(dy + 2) * 5 + (dx + 2)] = s->psi[gidx(s, x + dx, y + dy)];
-            if (p->gradient == 1) {
-                or_gradient5x5(patch, F);
-            } else {
-                double p9[9];
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) p9[(dy + 1) * 3 + (dx + 1)] = patch[(dy + 2) * 5 + (dx + 2)];
-                or_gradient3x3(p9, F);
-            }
+            double F[2];
+            node_gradient(s, x, y, F);
             if (p->bc_y == OR_BCY_WALLS && p->contact_angle >= 0.0 && (y == 0 || y == ny - 1)) {
                 /* wetting (Sec. 2.4, R11): the wall normal points into the fluid and
                    the gradient points into red, so the angle between them is the
@@ -749,7 +776,7 @@ static void pass_collide(or_sim *s)
                 F[0] = Fw[0];
                 F[1] = Fw[1];
             }
-            double psi = patch[12];
+            double psi = s->psi[gidx(s, x, y)];
             double w = or_omega_eff(psi, s->omega[0], s->omega[1], p->delta);
             double A = p->sigma > 0.0 ? 9.0 * p->sigma * w / 4.0 : p->A;
 
@@ -860,6 +887,28 @@ void or_moments(or_sim *s, double *rho_r, double *rho_b, double *ux, double *uy,
     }
 }
 
+void or_gradients(or_sim *s, double *Fx, double *Fy, double *dqxdx, double *dqydy)
+{
+    int nx = s->p.nx, ny = s->p.ny;
+    size_t n = (size_t)nx * ny;
+    macro_passes(s);
+    pass_color_field(s);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t c = (size_t)y * nx + x;
+            double F[2];
+            node_gradient(s, x, y, F);
+            if (Fx) Fx[c] = F[0];
+            if (Fy) Fy[c] = F[1];
+            for (int k = 0; k < 2 && s->p.ns_correction; ++k) {
+                double dqx, dqy;
+                q_divergence(s, k, x, y, &dqx, &dqy);
+                if (dqxdx) dqxdx[k * n + c] = dqx;
+                if (dqydy) dqydy[k * n + c] = dqy;
+            }
+        }
+}
+
 void or_get_pops(const or_sim *s, double *out)
 {
     memcpy(out, s->post, 18 * (size_t)s->p.nx * s->p.ny * sizeof(double));
@@ -868,6 +917,18 @@ void or_get_pops(const or_sim *s, double *out)
 void or_set_pops(or_sim *s, const double *in)
 {
     memcpy(s->post, in, 18 * (size_t)s->p.nx * s->p.ny * sizeof(double));
+}
+
+/* A storage model, not part of the method: each stored population rounded
+ * to the nearest FP32 number, which is what FP32 storage alone does to the
+ * FP64 state after a step.  The parity tests measure with it how much the
+ * flow amplifies rounding. */
+void or_round_f32(or_sim *s)
+{
+    long n = 18 * (long)s->p.nx * s->p.ny;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c)
+        s->post[c] = (double)(float)s->post[c];
 }
 
 long or_step_count(const or_sim *s) { return s->step; }

@@ -52,7 +52,19 @@ typedef struct {
                                the MRT source U^k, Hermite terms of the Zou-He completion) */
     int gradient;           /* 0: eq. (colorGradient), nearest neighbours; 1: the second-neighbour
                                8th-order isotropic stencil (R15) */
+    int alt;                /* alternative readings of rules the paper leaves open, for measuring how
+                               much they matter (0: the readings R1-R15 used everywhere); bits: */
 } or_params;
+
+/* or_params.alt bits */
+enum {
+    OR_ALT_Q_WALL_ZERO = 1,     /* R14: Q ghost values beyond a wall are 0 (the wall is at rest) instead of
+                                   the colour field's extrapolation */
+    OR_ALT_ISO_EXTRAP = 2,      /* R15: the outer ghost row beyond a wall is the linear extrapolation
+                                   2 g - f of the inner ghost row g and the wall row f, not a copy of g */
+    OR_ALT_OUTLET_UPSTREAM = 4  /* R7: outlet colour fractions from the colour field of the node upstream
+                                   (x = nx - 2) at this step, not from the six populations streaming in */
+};
 
 typedef struct or_sim or_sim;
 
@@ -90,7 +102,15 @@ void    or_set_inlet_color(or_sim *s, const signed char *color_y); /* +1 red, -1
 void    or_step(or_sim *s, long nsteps);
 void    or_moments(or_sim *s, double *rho_r, double *rho_b, double *ux, double *uy, double *p);
 void    or_get_pops(const or_sim *s, double *out);      /* [2][9][ny][nx] */
+/* The gradients the next step would use, from the stored state (the state is
+ * not advanced): the colour gradient F ([ny][nx] each, before any contact-
+ * angle turn) and, with the Navier-Stokes correction, dQx/dx and dQy/dy of
+ * each colour ([2][ny][nx] each; NULL to skip). */
+void    or_gradients(or_sim *s, double *Fx, double *Fy, double *dqxdx, double *dqydy);
 void    or_set_pops(or_sim *s, const double *in);
+/* Round the stored populations to FP32 (a storage model for measuring how
+ * the flow amplifies rounding; no step of the method). */
+void    or_round_f32(or_sim *s);
 long    or_step_count(const or_sim *s);
 int     or_threads(void);
 

@@ -700,7 +700,13 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
         rb = red ? 0.f : rin;
     } else if (xc.outlet) {
         const float vr = kn[0] * S.inv_rho0[0], vb = kn[1] * S.inv_rho0[1];
-        const float chir = vr / (vr + vb), chib = vb / (vr + vb);
+        // colour fractions, (phi + 1) / 2 with phi in [-1, 1]: clamped, so that
+        // a trace colour whose incoming populations sum below zero (16-bit
+        // storage leaves such residuals on rest populations) is absent
+        // instead of negative, which the recolouring would amplify
+        float chir = vr / (vr + vb), chib = vb / (vr + vb);
+        chir = chir < 0.f ? 0.f : (chir > 1.f ? 1.f : chir);
+        chib = chib < 0.f ? 0.f : (chib > 1.f ? 1.f : chib);
         rr = chir * S.rho_out[0];
         rb = chib * S.rho_out[1];
         const float rho_o = rr + rb;

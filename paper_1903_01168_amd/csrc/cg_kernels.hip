@@ -2,10 +2,15 @@
 //
 //  k_step      one fused time step over a set of lattices ("slots"): pull
 //              gather + boundary completion, colour field, S2I4 gradient,
-//              omega_eff, BGK/MRT, perturbation, recolouring, store.  Every
-//              wavefront owns 60 columns (plus 2 overlap columns on each side;
-//              58 and 3 with the second-neighbour gradient)
-//              of a strip of rows and marches up the strip on its own.
+//              omega_eff, BGK/MRT, perturbation, recolouring, store, in two
+//              flavours with the same results: halo lanes (a wavefront owns
+//              the middle 60 of its lanes' columns, 58 with the
+//              second-neighbour gradient, and marches along its strip on
+//              its own; for lattices that stay in the cache) and block
+//              exchange (a wavefront owns one whole 64-column block of the
+//              layout and a workgroup's wavefronts trade edge columns
+//              through LDS, one barrier per row; whole cache lines written,
+//              for lattices beyond the cache).
 //  k_init      equilibrium initialisation from FP32 fields.
 //  k_moments   fields at the current step (+ FP64 per-block diagnostics).
 //  k_reduce    fixed-order FP64 reduction of the per-block partials.
