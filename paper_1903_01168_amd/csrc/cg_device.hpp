@@ -100,7 +100,7 @@ struct SlotDesc {
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 
 // Cache policy bits of the population loads and stores (0: default; the
-// non-temporal bit (2) measured slower for this access pattern).
+// block-exchange step stores with the non-temporal bit, see k_step).
 #ifndef CG_LOAD_POLICY
 #define CG_LOAD_POLICY 0
 #endif
@@ -1102,13 +1102,19 @@ struct Keep18 {
 
 // FP32 storage: the sink stores each output pair as it comes, keeping only
 // the four diagonal pairs, which take the node's colour-mass residual at the
-// end (the exact bookkeeping of conserve(), in the same order).
+// end (the exact bookkeeping of conserve(), in the same order).  POL: cache
+// policy bits of the stores.
+template <int POL = CG_STORE_POLICY>
 struct StoreF32 {
     const SlotDesc &S;
     const Halves &h;
     NodeAt at;
     double sr, sb;
     float kr[4], kb[4];
+    static __device__ __forceinline__ void store_f32p(float v, Rsrc r, uint32_t voff, uint32_t soff)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, POL);
+    }
     __device__ __forceinline__ StoreF32(const SlotDesc &s, const Halves &hh, const NodeAt &a)
         : S(s), h(hh), at(a), sr(0.0), sb(0.0) {}
     __device__ __forceinline__ void operator()(int i, float vr, float vb)
@@ -1116,8 +1122,8 @@ struct StoreF32 {
         sr += (double)vr;
         sb += (double)vb;
         if (i < 5) {
-            Codec<ST_F32>::store(vr, h.r[0], at.col, plane_off<ST_F32>(i) + at.row, S, 0, vclass(i));
-            Codec<ST_F32>::store(vb, h.r[1], at.col, plane_off<ST_F32>(i) + at.row, S, 1, vclass(i));
+            store_f32p(vr, h.r[0], at.col, plane_off<ST_F32>(i) + at.row);
+            store_f32p(vb, h.r[1], at.col, plane_off<ST_F32>(i) + at.row);
         } else {
             kr[i - 5] = vr;
             kb[i - 5] = vb;
@@ -1128,8 +1134,8 @@ struct StoreF32 {
         const float qr = (float)((nd.mr - sr) * 0.25), qb = (float)((nd.mb - sb) * 0.25);
 #pragma unroll
         for (int i = 5; i < 9; ++i) {
-            Codec<ST_F32>::store(kr[i - 5] + qr, h.r[0], at.col, plane_off<ST_F32>(i) + at.row, S, 0, vclass(i));
-            Codec<ST_F32>::store(kb[i - 5] + qb, h.r[1], at.col, plane_off<ST_F32>(i) + at.row, S, 1, vclass(i));
+            store_f32p(kr[i - 5] + qr, h.r[0], at.col, plane_off<ST_F32>(i) + at.row);
+            store_f32p(kb[i - 5] + qb, h.r[1], at.col, plane_off<ST_F32>(i) + at.row);
         }
     }
 };
