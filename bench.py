@@ -371,7 +371,9 @@ def run_serve(args, log):
                              aggregate_mlups=lu.sum() / serial_span / 1e6,
                              solve_mlups=lu.sum() / sum(service) / 1e6, unstable=unstable32),
             # |dp(served, 16-bit) - dp(serial FP32)| / (sigma / R) per bubble request: all of
-            # them (many still in their pressure transient) and those that have settled
+            # them (many still in their pressure transient) and those whose FP32 jump is within
+            # 10% of Laplace at the request's step count (a bubble can pass there mid-oscillation;
+            # --workload serve-laplace tells settled ones by running FP32 four times longer)
             laplace_dp_vs_fp32=dict(n=len(dpdiff), max=max(dpdiff) if dpdiff else None,
                                     p99=pct(dpdiff, 99), median=pct(dpdiff, 50),
                                     over_1pct=int(sum(d > 0.01 for d in dpdiff)),
@@ -428,13 +430,85 @@ def main_serve(args, log):
     print(json.dumps(out), flush=True)
 
 
+def main_serve_laplace(args, log):
+    """The serving mix's bubble requests served twice through the server, in
+    16-bit and in FP32 storage (the same groups and chunks: grouping is
+    bit-neutral, so the two differ by storage alone), and their Laplace
+    pressure jumps compared: |dp(16-bit) - dp(FP32)| / (sigma / R).  Every
+    request whose difference exceeds 1% is run again in FP32 on the
+    single-lattice path for four times its steps, to tell a storage error from
+    a bubble that has not settled (FP32's own jump still moving by more than
+    1% of sigma / R)."""
+    import numpy as np
+    import torch
+    from paper_1903_01168_amd import capi, serve
+    from paper_1903_01168_amd import workloads as W
+
+    capi.load()
+    torch.cuda.init()
+    trace = [r for r in W.serve_trace(seed=args.seed, n=args.requests, storage=args.storage)
+             if r["kind"] == "bubble"]
+    budget = int(args.hbm_budget_gib * (1 << 30))
+    res = {}
+    for st in (args.storage, "f32"):
+        t0 = time.perf_counter()
+        with serve.Server(budget, max_slots=args.max_slots, chunk_steps=args.chunk, storage=st) as s:
+            ids = [s.enqueue(dict(r["params"], storage=st), serve_init(r["geo"]), r["steps"]) for r in trace]
+            res[st] = [s.wait(i) for i in ids]
+        log(f"serve-laplace: {len(trace)} bubbles served in {st} in {time.perf_counter() - t0:.1f} s")
+    rows, diffs = [], []
+    for r, a, b in zip(trace, res[args.storage], res["f32"]):
+        x, y = dp_of(a["diag"], r), dp_of(b["diag"], r)
+        row = dict(i=r["index"], gamma=r["gamma"], n=r["params"]["nx"], steps=r["steps"],
+                   status16=a["status"], status32=b["status"])
+        if x is None or y is None or a["status"] != capi.LBM_OK or b["status"] != capi.LBM_OK:
+            row["compared"] = False
+            rows.append(row)
+            continue
+        row.update(compared=True, diff=abs(x[0] - y[0]) / y[1], lap32=y[0] / y[1] - 1.0, lap16=x[0] / x[1] - 1.0)
+        diffs.append(row["diff"])
+        rows.append(row)
+    outliers = [row for row in rows if row.get("compared") and row["diff"] > 0.01]
+    for row, r in ((row, next(t for t in trace if t["index"] == row["i"])) for row in outliers):
+        p = dict(r["params"], storage="f32")
+        rr, rb = W.geo_fields(r["geo"], p["nx"], p["ny"])
+        with capi.Lattice(p) as g:
+            g.init(rr, rb)
+            g.step(4 * r["steps"])
+            d = g.diag(check=False)
+            y = None
+            if d["n_nonfinite"] == 0 and d["area_r"] > 0:
+                R = math.sqrt(d["area_r"] / math.pi)
+                d = g.diag(circle=(r["geo"]["cx"], r["geo"]["cy"], R - 4.0, R + 4.0), check=False)
+                y = dp_of(d, r)
+        b = dp_of(res["f32"][trace.index(r)]["diag"], r)
+        row["lap32_4x"] = y[0] / y[1] - 1.0 if y else None
+        row["fp32_moves_4x"] = abs(y[0] - b[0]) / y[1] if y else None
+        log(f"serve-laplace outlier {row}")
+    settled_out = [row for row in outliers if row["fp32_moves_4x"] is not None and row["fp32_moves_4x"] <= 0.01]
+    out = {
+        "workload": f"serving mix, bubble requests only: {len(trace)} of {args.requests} "
+                    f"(gamma in {{1,10,100,1000}}, 64^2..1024^2, 1000..50000 steps)",
+        "storage": args.storage, "compared": len(diffs),
+        "not_compared": sum(1 for row in rows if not row.get("compared")),
+        "diff_median": pct(diffs, 50), "diff_p99": pct(diffs, 99), "diff_max": max(diffs) if diffs else None,
+        "over_1pct": len(outliers),
+        "over_1pct_with_fp32_settled": len(settled_out),
+        "outliers": outliers,
+        "definition": "diff = |dp(16-bit) - dp(FP32)| / (sigma / R), both served through the server; "
+                      "fp32_moves_4x = |dp(FP32, 4 x steps) - dp(FP32)| / (sigma / R)",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="channel",
-                    help="channel (default), sweep512, slug, hbm8192, bubble64 or serve")
+                    help="channel (default), sweep512, slug, hbm8192, bubble64, serve, or serve-laplace "
+                         "(16-bit against FP32 storage on the serving mix's bubbles)")
     ap.add_argument("--storage", default=None, choices=["f32", "f16s", "bf16s"],
                     help="population storage (default f32; f16s for the serving mix)")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
@@ -470,13 +544,16 @@ def main():
         sys.exit(2)
 
     if args.storage is None:
-        args.storage = "f16s" if args.workload == "serve" else "f32"
+        args.storage = "f16s" if args.workload in ("serve", "serve-laplace") else "f32"
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
     if args.workload == "serve":
         main_serve(args, log)
+        return
+    if args.workload == "serve-laplace":
+        main_serve_laplace(args, log)
         return
 
     import torch

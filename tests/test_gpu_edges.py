@@ -4,18 +4,20 @@ wavefront block and the workgroup span, walls on one- and two-row channels,
 open channels from two columns wide to widths around a block (the outlet
 column then one of the halo nodes of the block next to it), one fluid
 only, no surface tension, recolouring
-strength beta at both ends of its range, and zero steps.  Bound: the FP32
-bound of the static bubble (max |d rho| / rho <= 1e-5, max |d u| <= 1e-6);
+strength beta at both ends of its range, and zero steps.  Bounds (tests/bounds.py):
+the FP32 bound of the static bubble (max |d rho| / rho <= 1e-5, max |d u| <= 1e-6);
 the rough random fields of the size cases are compared population by
-population over one step from a developed oracle state (2e-6 rho0_max) and
-over their first 20 steps to that bound or, where it is exceeded, 50 times
-the oracle's own sensitivity to FP32 storage rounding."""
+population over one step from a developed oracle state (2e-6 rho0_max: one
+step injects about 24 ulps, 1.4e-6 relative) and over their first 20 steps
+to the fixed bound or, where it is exceeded, FACTOR times the oracle's own
+sensitivity to FP32 storage rounding."""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
+from bounds import Bound, oracle_run
 from paper_1903_01168_amd import capi
 from paper_1903_01168_amd import workloads as W
 
@@ -53,21 +55,6 @@ def _errors(om, gm):
     return drho, du
 
 
-def _bounds(p, rr, rb, ux, uy, steps=STEPS):
-    """The fixed FP32 bound, or 50 times the change that rounding its stored
-    populations to FP32 after every step causes in the oracle (rough random
-    fields amplify rounding; the GPU rounds in its arithmetic as well)."""
-    def run(quantise):
-        s = oracle.Sim(**p).init(rr, rb, ux, uy)
-        for _ in range(steps):
-            s.step(1)
-            if quantise:
-                s.set_pops(s.get_pops().astype(np.float32).astype(np.float64))
-        return s.moments()
-    s_rho, s_u = _errors(run(False), run(True))
-    return max(1e-5, 50 * s_rho), max(1e-6, 50 * s_u)
-
-
 SIZES = [(1, 1, "periodic"), (1, 9, "periodic"), (9, 1, "periodic"), (2, 2, "periodic"), (5, 1, "walls"),
          (5, 2, "walls"), (1, 6, "walls"), (59, 7, "periodic"), (60, 7, "periodic"), (61, 7, "walls"),
          (119, 5, "periodic"), (121, 5, "walls"), (241, 3, "periodic"), (300, 1, "walls"),
@@ -81,7 +68,7 @@ def test_degenerate_and_ragged_sizes(nx, ny, bcy):
     """Every population after one GPU step from the oracle's state at step
     STEPS - 1 within 2e-6 rho0_max (a wrong neighbour, wrap or wall would
     show at O(1)); and the fields after SHORT steps from the initial rough
-    field within the bounds of _bounds.  (Over STEPS steps some of these
+    field within the parity bound (Bound).  (Over STEPS steps some of these
     rough fields amplify any rounding difference by two orders of magnitude
     at once, e.g. 241 x 3: 4e-7 at step 20, 2.5e-5 at step 40, with every
     single step at FP32 level, so the multi-step comparison stops earlier.)"""
@@ -93,21 +80,18 @@ def test_degenerate_and_ragged_sizes(nx, ny, bcy):
     state = o.get_pops()
     o.step(1)
     ref = o.get_pops()
-    tol = None
+    om = oracle_run(p, rr, rb, ux, uy, steps=SHORT)
+    bound = Bound(om, lambda: oracle_run(p, rr, rb, ux, uy, steps=SHORT, round_f32=True), tag="gpu-edges")
     for launch in ((64, 0), (256, 1), (1024, 2)):
         with capi.Lattice(p) as g:
             g.set_launch(*launch)
             g.set_pops(state)
             g.step(1)
             err = float(np.abs(g.get_pops() - ref).max())
-        drho, du = _errors(*_run(p, rr, rb, ux, uy, steps=SHORT, launch=launch))
-        if (drho > 1e-5 or du > 1e-6) and tol is None:
-            tol = _bounds(p, rr, rb, ux, uy, steps=SHORT)
-        t_rho, t_u = tol or (1e-5, 1e-6)
-        say(f"{nx}x{ny} {bcy} tile {launch[0]}: one step max |dN| {err:.2e}; {SHORT} steps drho/rho {drho:.2e} "
-            f"du {du:.2e} (bounds {t_rho:.1e}, {t_u:.1e})")
+        _, gm = _run(p, rr, rb, ux, uy, steps=SHORT, launch=launch)
+        say(f"{nx}x{ny} {bcy} tile {launch[0]}: one step max |dN| {err:.2e}")
         assert err <= 2e-6 * 3.0
-        assert drho <= t_rho and du <= t_u
+        bound.check(f"{nx}x{ny} {bcy} tile {launch[0]}, {SHORT} steps", gm)
 
 
 @pytest.mark.parametrize("nx", [2, 63, 64, 65, 66, 129])

@@ -3,16 +3,17 @@ oracle: rough random fields on every boundary kind and degenerate sizes
 (two launch shapes), with the contact angle and with the Navier-Stokes
 correction, the open channel, one step from a developed oracle state, the
 static bubble's spurious currents, launch-shape independence and mixed
-batches.  Bounds as for the nearest-neighbour stencil: the FP32 bound of
-the static bubble (max |d rho| / rho <= 1e-5, max |d u| <= 1e-6), or 50
-times the oracle's own sensitivity to FP32 storage rounding where rough
-fields amplify rounding."""
+batches.  Bounds as for the nearest-neighbour stencil (tests/bounds.py): the
+FP32 bound of the static bubble (max |d rho| / rho <= 1e-5, max |d u| <=
+1e-6), or FACTOR times the oracle's own sensitivity to FP32 storage rounding
+where rough fields amplify rounding."""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
+from bounds import Bound
 from paper_1903_01168_amd import capi
 from paper_1903_01168_amd import workloads as W
 
@@ -23,23 +24,11 @@ def say(*a):
     print("[gpu-iso]", *a, file=sys.stderr, flush=True)
 
 
-def _errors(om, gm):
-    rho_o = om["rho_r"] + om["rho_b"]
-    drho = float(np.max(np.abs(gm["rho_r"] + gm["rho_b"] - rho_o) / rho_o))
-    du = float(max(np.max(np.abs(gm["ux"] - om["ux"])), np.max(np.abs(gm["uy"] - om["uy"]))))
-    return drho, du
-
-
 def _oracle(p, rr, rb, ux, uy, steps, color=None, quantise=False):
     s = oracle.Sim(**p).init(rr, rb, ux, uy)
     if color is not None:
         s.set_inlet_color(color)
-    if not quantise:
-        s.step(steps)
-    else:
-        for _ in range(steps):
-            s.step(1)
-            s.set_pops(s.get_pops().astype(np.float32).astype(np.float64))
+    s.step(steps, round_f32=quantise)
     return s.moments()
 
 
@@ -56,15 +45,9 @@ def _gpu(p, rr, rb, ux, uy, steps, color=None, launch=None):
 
 def _check(name, p, rr, rb, ux, uy, steps, color=None, launches=((64, 0), (256, 3))):
     om = _oracle(p, rr, rb, ux, uy, steps, color)
-    tol = None
+    bound = Bound(om, lambda: _oracle(p, rr, rb, ux, uy, steps, color, quantise=True), tag="gpu-iso")
     for launch in launches:
-        drho, du = _errors(om, _gpu(p, rr, rb, ux, uy, steps, color, launch))
-        if (drho > 1e-5 or du > 1e-6) and tol is None:
-            s_rho, s_u = _errors(om, _oracle(p, rr, rb, ux, uy, steps, color, quantise=True))
-            tol = (max(1e-5, 50 * s_rho), max(1e-6, 50 * s_u))
-        t_rho, t_u = tol or (1e-5, 1e-6)
-        say(f"{name} tile {launch}: drho/rho {drho:.2e} du {du:.2e} (bounds {t_rho:.1e}, {t_u:.1e})")
-        assert drho <= t_rho and du <= t_u, (name, launch)
+        bound.check(f"{name} tile {launch}", _gpu(p, rr, rb, ux, uy, steps, color, launch))
 
 
 CASES = {

@@ -4,8 +4,8 @@ Zou-He term H) on the GPU against the FP64 oracle.
 Parity to the FP32 bound of the static bubble (max |d rho| / rho <= 1e-5,
 max |d u| <= 1e-6) on rough random fields (periodic, walls of both kinds,
 body force, density ratio 5), and on the stratified open channel (density
-ratio 5, velocity inlet and pressure outlet) to that bound or 50 times the
-oracle's own sensitivity to FP32 storage rounding.  A batch of lattices of
+ratio 5, velocity inlet and pressure outlet) to that bound or FACTOR times
+the oracle's own sensitivity to FP32 storage rounding (tests/bounds.py).  A batch of lattices of
 both kinds steps each run of one kind with its own kernel variant, and each
 lattice gets exactly its result alone.  Validation: on the GPU a shear wave, a Taylor-Green
 vortex and a standing sound wave decay at the Chapman-Enskog rates of the
@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
+from bounds import Bound, oracle_run
 from paper_1903_01168_amd import capi
 from paper_1903_01168_amd import workloads as W
 
@@ -78,21 +79,10 @@ def test_open_channel_stratified():
         g.set_inlet_color(color)
         g.step(400)
         gm = g.moments()
-    om = s.moments()
-    drho, du = _errors(om, gm)
     # the interface meets the outlet: there the flow amplifies rounding, and
-    # the bound is 50 times the change that rounding the oracle's stored
-    # populations to FP32 after every step causes (as for the rough fields
-    # of the edge-case tests), or the fixed one
-    q = oracle.Sim(**p).init(rr, rb)
-    q.set_inlet_color(color)
-    for _ in range(400):
-        q.step(1)
-        q.set_pops(q.get_pops().astype(np.float32).astype(np.float64))
-    s_rho, s_u = _errors(om, q.moments())
-    t_rho, t_u = max(1e-5, 50 * s_rho), max(1e-6, 50 * s_u)
-    say(f"open channel: drho/rho {drho:.2e} du {du:.2e} (bounds {t_rho:.1e}, {t_u:.1e})")
-    assert drho <= t_rho and du <= t_u
+    # the bound is the fixed one or FACTOR times the oracle's own sensitivity
+    Bound(s.moments(), lambda: oracle_run(p, rr, rb, steps=400, color=color, round_f32=True),
+          tag="gpu-nsc").check("open channel", gm)
 
 
 def test_one_step_from_oracle_state():
@@ -111,6 +101,38 @@ def test_one_step_from_oracle_state():
     err = float(np.abs(got - ref).max())
     say(f"one step: max |dN| {err:.2e}")
     assert err <= 2e-6 * max(p["rho0_r"], p["rho0_b"])
+
+
+@pytest.mark.parametrize("walls", ["walls", "freeslip", "slip_top"])
+def test_one_step_open_channel_from_oracle_state(walls):
+    """One GPU step from a developed oracle state of the stratified open
+    channel with the correction (inlet and outlet meet the walls at four
+    corners): every population within 2e-6 rho0_max; the node of the largest
+    difference is printed."""
+    ny, nx, gamma = 24, 120, 5.0
+    p = W.params(nx=nx, ny=ny, bc_x="open", bc_y=walls, rho0_r=gamma, rho0_b=1.0, tau_r=0.6, tau_b=0.75,
+                 A=1e-3, u_in_r=0.03, u_in_b=0.005, p_out=0.48, collision="mrt", ns_correction=True)
+    color = np.where(np.arange(ny) < ny // 2, 1, -1).astype(np.int8)
+    rr = np.where(color[:, None] > 0, gamma, 0.0) * np.ones((1, nx))
+    rb = np.where(color[:, None] > 0, 0.0, 1.0) * np.ones((1, nx))
+    o = oracle.Sim(**p).init(rr, rb)
+    o.set_inlet_color(color)
+    o.step(3000)
+    state = o.get_pops()
+    o.step(1)
+    ref = o.get_pops()
+    for launch in ((64, 0), (256, 2)):
+        with capi.Lattice(p) as g:
+            g.set_launch(*launch)
+            g.set_pops(state)
+            g.set_inlet_color(color)
+            g.step(1)
+            got = g.get_pops()
+        d = np.abs(got - ref)
+        k, i, y, x = np.unravel_index(np.argmax(d), d.shape)
+        say(f"open channel {walls} tile {launch[0]}: one step max |dN| {d.max():.2e} at colour {k} "
+            f"direction {i} (x, y) = ({x}, {y})")
+        assert d.max() <= 2e-6 * gamma
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])

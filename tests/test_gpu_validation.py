@@ -19,10 +19,26 @@ Inlet/outlet (Sec. 2.5 item 3 verification): a 500 x 50 channel, heavy
 Navier-Stokes correction (without it the plain schemes, in the FP64 oracle
 as on the GPU, send a pressure wave through the outlet and blow up within
 50000 steps here).  The prescribed inlet velocity of each phase and the
-outlet pressure are recovered within 2% (the paper's bound; exactly on the
-boundary nodes, within 0.1% one node inside the outlet), and the run stays
-finite with max |u| < 0.1."""
+outlet pressure are recovered within 2% (the paper's bound) on the boundary
+nodes, where the Zou-He completion makes them exact by construction, and the
+outlet pressure one node in (not exact: 0.9996 of p_out).  The inflow does
+not stay plug-shaped: one node in, the mean over the heavy phase's rows is
+3.2% above its prescribed velocity and the light phase's 11.5% (no-slip
+walls; 3.1% and 11.4% with free-slip walls: the 6:1 velocity jump at the
+interface reshapes the profile at once), above the paper's 2%; this is the
+method's result, not the kernels': the GPU reproduces every one of these
+observables of the FP64 oracle (tests/golden/e1_channel.json, written by
+make_e1_channel.py) within E1_AGREE = 2e-4, one hundredth of the paper's
+2% (measured: up to 1.8e-4, the light phase two nodes in after 50000 steps
+with free-slip walls; 3e-5 and less elsewhere).  That is not the per-node
+parity rule of tests/bounds.py: over tens of thousands of steps of a nearly
+steady open flow, FP32 rounding that falls the same way at every node and
+step shifts such row means coherently (the FP64 oracle with FP32-rounded
+storage moves them by only 1e-8, its roundings having random signs).  The run
+stays finite with max |u| < 0.1."""
+import json
 import math
+import os
 import sys
 
 import numpy as np
@@ -34,6 +50,7 @@ from paper_1903_01168_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 SIGMA = 0.01
+E1_AGREE = 2e-4
 
 
 def say(*a):
@@ -91,18 +108,26 @@ def test_inlet_outlet_recovers_prescribed_values(walls):
     rr = np.where(color[:, None] > 0, gamma, 0.0) * np.ones((1, nx))
     rb = np.where(color[:, None] > 0, 0.0, 1.0) * np.ones((1, nx))
     heavy = color > 0
+    with open(os.path.join(os.path.dirname(__file__), "golden", "e1_channel.json")) as f:
+        stored = json.load(f)
+    gold, gold32 = stored["values"][walls], stored["values_fp32_storage"][walls]
     with capi.Lattice(p) as g:
         g.init(rr, rb)
         g.set_inlet_color(color)
         for t in (10000, 25000, 50000):
             g.step(t - g.steps_done)
             m = g.moments()
-            vh = m["ux"][heavy, 0].mean() / uh
-            vl = m["ux"][~heavy, 0].mean() / ul
-            po, po1 = m["p"][:, -1].mean() / 0.48, m["p"][:, -2].mean() / 0.48
+            got = {"p_out": m["p"][:, -1].mean() / 0.48, "p_out_1": m["p"][:, -2].mean() / 0.48}
+            for x in (0, 1, 2):
+                got[f"v_heavy_{x}"] = m["ux"][heavy, x].mean() / uh
+                got[f"v_light_{x}"] = m["ux"][~heavy, x].mean() / ul
+            ref, ref32 = gold[str(t)], gold32[str(t)]
             umax = float(np.hypot(m["ux"], m["uy"]).max())
-            say(f"{walls} step {t}: inlet heavy {vh:.5f} light {vl:.5f}, outlet p {po:.7f} "
-                f"(one node in {po1:.5f}), max |u| {umax:.3f}")
-            assert abs(vh - 1) <= 0.02 and abs(vl - 1) <= 0.02
-            assert abs(po - 1) <= 0.02 and abs(po1 - 1) <= 1e-3
+            say(f"{walls} step {t}: " + ", ".join(f"{k} {v:.5f} (FP64 {ref[k]:.5f})" for k, v in got.items())
+                + f", max |u| {umax:.3f}")
+            assert abs(got["v_heavy_0"] - 1) <= 0.02 and abs(got["v_light_0"] - 1) <= 0.02
+            assert abs(got["p_out"] - 1) <= 0.02
+            assert abs(got["p_out_1"] - 1) <= 0.02
+            for k, v in got.items():
+                assert abs(v - ref[k]) <= E1_AGREE, (k, v, ref[k], abs(ref32[k] - ref[k]))
             assert umax < 0.1

@@ -168,3 +168,20 @@ def test_ghost_rows_of_q(orc, alt):
     assert np.allclose(dqx[1:NY - 1], DQ / 2, atol=1e-16, rtol=0)
     assert np.allclose(g["dqydy"], 0.0, atol=1e-17, rtol=0)
     assert np.allclose(g["dqxdx"][1], 0.0, atol=0, rtol=0)
+
+
+def test_fp32_storage_model_rounds_each_population_once(orc):
+    """The parity bounds' storage model: a step with round_f32 is the plain
+    step followed by rounding every stored population to the nearest FP32
+    number (and nothing else)."""
+    p = W.params(nx=40, ny=20, rho0_r=1.0, rho0_b=3.0, tau_r=0.7, tau_b=0.9, A=1e-3)
+    rr, rb, ux, uy = W.random_fields(40, 20, seed=3, rho0_r=1.0, rho0_b=3.0)
+    a = orc.Sim(**p).init(rr, rb, ux, uy)
+    b = orc.Sim(**p).init(rr, rb, ux, uy)
+    for _ in range(5):
+        a.step(1)
+        a.set_pops(a.get_pops().astype(np.float32).astype(np.float64))
+    b.step(5, round_f32=True)
+    assert np.array_equal(a.get_pops(), b.get_pops())
+    c = orc.Sim(**p).init(rr, rb, ux, uy).step(5)
+    assert not np.array_equal(c.get_pops(), b.get_pops())
