@@ -58,7 +58,7 @@ int validate(const lbm_params *p, std::string &msg);
 Layout layout(const lbm_params *p);
 void fill_desc(const lbm_params *p, cgd::SlotDesc &d);
 int default_tx(int nx, int ny);
-int xch_tx(int nx, int variant);
+int xch_tx(int nx, int ny, int variant);
 // Population bytes of a launch (both buffers of every lattice) beyond which
 // FP32 launches take the exchange flavour of the step (KV_XCH).
 constexpr size_t kXchBytes = 256ull << 20;
