@@ -171,3 +171,14 @@ def test_bench_refuses_more_than_one_gpu():
     assert out.returncode == 2
     line = json.loads(out.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+@pytest.mark.parametrize("storage,per_node", [("f32", 36), ("f16s", 20), ("bf16s", 20)])
+def test_largest_lattice_accepted_next_rejected(lib, storage, per_node):
+    """A colour half of a buffer must stay below 4 GiB (32-bit buffer offsets):
+    at nx = 65536 the tallest lattice accepted is the last one whose half is
+    below 2^32 - 4096 bytes, one row more is rejected."""
+    nx = 65536
+    ny = ((1 << 32) - 4096 - 1) // (per_node * nx)
+    assert _bytes(W.params(nx=nx, ny=ny, A=1e-3, storage=storage)) > 0
+    assert _bytes(W.params(nx=nx, ny=ny + 1, A=1e-3, storage=storage)) == 0

@@ -4,7 +4,8 @@ wavefront block and the workgroup span, walls on one- and two-row channels,
 open channels from two columns wide to widths around a block (the outlet
 column then one of the halo nodes of the block next to it), one fluid
 only, no surface tension, recolouring
-strength beta at both ends of its range, and zero steps.  Bounds (tests/bounds.py):
+strength beta at both ends of its range, zero steps, and the largest lattices the
+ABI accepts.  Bounds (tests/bounds.py):
 the FP32 bound of the static bubble (max |d rho| / rho <= 1e-5, max |d u| <= 1e-6);
 the rough random fields of the size cases are compared population by
 population over one step from a developed oracle state (2e-6 rho0_max: one
@@ -143,3 +144,53 @@ def test_zero_steps():
     om = oracle.Sim(**c["params"]).init(c["rho_r"], c["rho_b"], None, None).moments()
     drho, du = _errors(om, gm)
     assert drho <= 1e-6 and du <= 1e-7
+
+
+def test_maximum_size_fp32():
+    """The largest FP32 lattice the ABI accepts at 65536 columns (65536 x 1820:
+    a colour half of a buffer just below 4 GiB, so the last rows use the
+    largest 32-bit offsets; the planned block-exchange launch): a stratified
+    state uniform in x under a body force stays uniform in x bit for bit over
+    20 steps, and its columns match the oracle on a 64-column lattice."""
+    nx, ny, steps = 65536, 1820, 20
+    kw = dict(bc_y="walls", rho0_r=1.0, rho0_b=3.0, tau_r=0.8, tau_b=0.9, A=1e-3, gx=1e-5)
+    band = ((np.arange(ny) // 91) % 2 == 0)[:, None]          # 20 bands, 19 interfaces
+    col_r, col_b = np.where(band, 1.0, 0.0), np.where(band, 0.0, 3.0)
+    with capi.Lattice(W.params(nx=nx, ny=ny, **kw)) as g:
+        g.init(np.ascontiguousarray(np.broadcast_to(col_r, (ny, nx))),
+               np.ascontiguousarray(np.broadcast_to(col_b, (ny, nx))))
+        g.step(steps)
+        gm = g.moments()
+    for k in ("rho_r", "rho_b", "ux", "uy"):
+        assert np.array_equal(gm[k], np.broadcast_to(gm[k][:, :1], gm[k].shape)), k
+    o = oracle.Sim(**W.params(nx=64, ny=ny, **kw)).init(np.repeat(col_r, 64, axis=1), np.repeat(col_b, 64, axis=1),
+                                                        None, None)
+    o.step(steps)
+    om = o.moments()
+    keys = ("rho_r", "rho_b", "ux", "uy")
+    drho, du = _errors({k: om[k][:, :1] for k in keys}, {k: gm[k][:, :1] for k in keys})
+    say(f"{nx}x{ny} FP32: x-uniform bit for bit; column against the oracle drho/rho {drho:.2e} du {du:.2e}")
+    assert drho <= 1e-5 and du <= 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_maximum_size_16bit(storage):
+    """The largest 16-bit lattice the ABI accepts at 65536 columns (65536 x
+    3276): finite after 20 steps, and each colour's mass within 1e-7 (the
+    dither depends on the node's position, so the state is not x-uniform)."""
+    nx, ny, steps = 65536, 3276, 20
+    band = ((np.arange(ny) // 91) % 2 == 0)[:, None]
+    rr = np.ascontiguousarray(np.broadcast_to(np.where(band, 1.0, 0.0), (ny, nx)))
+    rb = np.ascontiguousarray(np.broadcast_to(np.where(band, 0.0, 3.0), (ny, nx)))
+    m0 = (rr.sum(), rb.sum())
+    p = W.params(nx=nx, ny=ny, bc_y="walls", rho0_r=1.0, rho0_b=3.0, tau_r=0.8, tau_b=0.9, A=1e-3, gx=1e-5,
+                 storage=storage)
+    with capi.Lattice(p) as g:
+        g.init(rr, rb)
+        del rr, rb
+        g.step(steps)
+        d = g.diag(check=False)
+    dr, db = d["mass_r"] / m0[0] - 1, d["mass_b"] / m0[1] - 1
+    say(f"{nx}x{ny} {storage}: {d['n_nonfinite']} non-finite, colour mass {dr:+.1e} {db:+.1e}")
+    assert d["n_nonfinite"] == 0
+    assert abs(dr) <= 1e-7 and abs(db) <= 1e-7
