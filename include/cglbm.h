@@ -211,8 +211,9 @@ int lbm_set_launch(lbm_ctx *ctx, int32_t tile_x, int32_t strip_rows);
  * LDS and the workgroup's outer halo nodes gathered beside each row: whole
  * cache lines written, for lattices beyond the last-level cache), 0 = halo
  * lanes (each wavefront writes 60 columns and its outer lanes hold the
- * neighbour columns), -1 = planned (block exchange for FP32 storage when both
- * population buffers exceed 256 MiB).  Results do not depend on it.
+ * neighbour columns), -1 = planned (block exchange for FP32 storage without
+ * the Navier-Stokes correction when both population buffers exceed 256 MiB).
+ * Results do not depend on it.
  * Errors: LBM_E_INVAL for another mode. */
 int lbm_set_exchange(lbm_ctx *ctx, int32_t mode);
 /* The HIP stream of the context (a hipStream_t). */
@@ -237,7 +238,8 @@ void *lbm_stream(const lbm_ctx *ctx);
  * lbm_moments / lbm_diag / checkpoints on them stay valid.  tile_x: threads
  * per workgroup, 0 (planned per group), 64, 128, 256, 512 or 1024.  Each
  * group's step flavour is planned (lbm_set_exchange: block exchange for FP32
- * groups whose two buffers exceed 256 MiB). */
+ * groups without the Navier-Stokes correction whose two buffers exceed
+ * 256 MiB). */
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, int32_t tile_x, void *hip_stream, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t n);

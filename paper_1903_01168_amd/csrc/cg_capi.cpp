@@ -217,9 +217,15 @@ int default_tx(int nx, int ny) { return (long long)nx * ny >= (1LL << 22) ? 256 
 // its codec's arithmetic.  Measured on MI355X: 8192 x 512 channel 31.0k
 // against 27.4k MLUPS, 8192^2 bubble 35.0k against 27.7k; 4096 x 256 slug
 // (151 MB) 29.7k against 35.8k, 1024^2 bubble 30.3k against 36.7k.
+// The block exchange pays for FP32 lattices beyond the cache with the
+// nearest-neighbour gradient and no Navier-Stokes correction.  With the
+// correction it needs more than 128 VGPRs (3 wavefronts per SIMD, at most 8
+// per workgroup), and the halo lanes are faster (8192 x 512 channel: 27.9k
+// MLUPS against 22.7k); 16-bit storage is VALU-bound, where the per-row
+// barrier costs more than it saves (39.4k against 34.1k).
 bool plan_exchange(size_t bytes, int storage, int variant)
 {
-    return storage == LBM_STORE_F32 && !(variant & cgd::KV_ISO) && bytes > kXchBytes;
+    return storage == LBM_STORE_F32 && !(variant & (cgd::KV_ISO | cgd::KV_NSC)) && bytes > kXchBytes;
 }
 
 // Exchange flavour: the widest workgroup (up to 16 wavefronts, 1024 columns)
