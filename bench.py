@@ -40,11 +40,38 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_01168_amd", "csrc", f)
                   for f in ("cg_device.hpp", "cg_kernels.hip", "cg_capi.cpp", "cg_schedule.hpp")]
 
 
+def code_text(src):
+    """C++ source with its comments and blank lines removed and each run of
+    whitespace in a line made one space: what the compiler sees, so that an
+    edit of a comment leaves the kernel's identity (and the traffic measured
+    for it) unchanged."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":                                   # string or character literal
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(" ".join(ln.split()) for ln in "".join(out).splitlines() if ln.strip())
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -211,18 +211,16 @@ int default_tx(int nx, int ny) { return (long long)nx * ny >= (1LL << 22) ? 256 
 // through LDS) for FP32 launches whose populations (both buffers of every
 // lattice) exceed the 256 MB Infinity Cache: there each row of a plane must
 // be written in whole cache lines, and the halo-lane flavour's stores, which
-// split lines between wavefronts, cost a read-modify-write in DRAM.  Inside
-// the cache the halo lanes are faster (no barrier, no halo gather on the row's
-// critical path), and so they are for 16-bit storage, whose step is bound by
-// its codec's arithmetic.  Measured on MI355X: 8192 x 512 channel 31.0k
-// against 27.4k MLUPS, 8192^2 bubble 35.0k against 27.7k; 4096 x 256 slug
-// (151 MB) 29.7k against 35.8k, 1024^2 bubble 30.3k against 36.7k.
-// The block exchange pays for FP32 lattices beyond the cache with the
-// nearest-neighbour gradient and no Navier-Stokes correction.  With the
-// correction it needs more than 128 VGPRs (3 wavefronts per SIMD, at most 8
-// per workgroup), and the halo lanes are faster (8192 x 512 channel: 27.9k
-// MLUPS against 22.7k); 16-bit storage is VALU-bound, where the per-row
-// barrier costs more than it saves (39.4k against 34.1k).
+// split lines between wavefronts, cost a read-modify-write in DRAM (8192 x
+// 512 channel 33k against 27k MLUPS; 8192^2 bubble 36k against 28k).  The
+// halo lanes stay the choice inside the cache (no barrier, no halo gather on
+// the row's critical path: 4096 x 256 slug, 151 MB, 35.8k against 29.7k);
+// for 16-bit storage, whose step is bound by its codec's arithmetic and pays
+// more for the per-row barrier than it saves (channel 39.4k against 34.1k);
+// with the Navier-Stokes correction, whose exchange step needs more than
+// 128 VGPRs, 3 wavefronts per SIMD and at most 8 per workgroup (channel
+// 27.9k against 22.7k); and with the 25-point isotropic gradient, for which
+// the exchange flavour is not built (its two-column halo stays in lanes).
 bool plan_exchange(size_t bytes, int storage, int variant)
 {
     return storage == LBM_STORE_F32 && !(variant & (cgd::KV_ISO | cgd::KV_NSC)) && bytes > kXchBytes;
