@@ -127,7 +127,10 @@ __device__ __forceinline__ void step_nn(const SlotDesc *__restrict__ slots, int 
                                         int launch_idx)
 {
     const int tile = xcd_tile(blockIdx.x, total_tiles);
-    const SlotDesc S = slots[find_slot(slots, nslots, tile)];
+    // the lattice's descriptor is read in place (scalar loads where a field
+    // is used) rather than copied: a copy holds ~60 of its fields in SGPRs
+    // for the whole march and spills dozens of them into VGPR lanes
+    const SlotDesc &S = slots[find_slot(slots, nslots, tile)];
     if (launch_idx >= S.active_steps) return;   // uniform per workgroup
 
     // tiles of a lattice run x-fastest: concurrently resident workgroups then
@@ -436,7 +439,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
                                           int parity, int launch_idx)
 {
     const int tile = xcd_tile(blockIdx.x, total_tiles);
-    const SlotDesc S = slots[find_slot(slots, nslots, tile)];
+    const SlotDesc &S = slots[find_slot(slots, nslots, tile)];   // read in place, as in step_nn
     if (launch_idx >= S.active_steps) return;
 
     // tiles of a lattice run x-fastest: concurrently resident wavefronts then
