@@ -428,13 +428,20 @@ __device__ __forceinline__ XCols make_cols(const SlotDesc &S, int x)
 struct RowSrc {
     uint32_t off[3];
     int y;
+    int icol;   // the inlet colour of row y (+1 red, -1 blue; 0 without open x faces)
 };
 
+// inlet: the caller completes nodes of the inlet column with this row (its
+// inlet colour is then requested with the row's populations and used when
+// they have arrived, so that the completion waits for no load of its own)
 template <int ST>
-__device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y)
+__device__ __forceinline__ RowSrc make_row(const SlotDesc &S, int y, bool inlet)
 {
     RowSrc r;
     r.y = y;
+    r.icol = (inlet && (S.flags & F_XOPEN))
+                 ? (int)((const __attribute__((address_space(1))) int8_t *)S.inlet_color)[y]
+                 : 0;
     const bool per = S.flags & F_YPER;
 #pragma unroll
     for (int d = -1; d <= 1; ++d) {       // d = c_y
@@ -686,7 +693,7 @@ __device__ __forceinline__ Node finish(const SlotDesc &S, const Raw18<ST> &raw, 
     }
     float rr = (float)rho[0], rb = (float)rho[1];
     if (xc.inlet) {
-        const bool red = ((const __attribute__((address_space(1))) int8_t *)S.inlet_color)[rw.y] > 0;
+        const bool red = rw.icol > 0;
         const float vx = red ? S.u_in[0] : S.u_in[1];
         float *N = nd.n;
         const float rin = (N[0] + N[2] + N[4] + 2.f * (N[3] + N[6] + N[7])) / (1.f - vx);

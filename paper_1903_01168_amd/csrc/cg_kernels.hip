@@ -149,6 +149,9 @@ __device__ __forceinline__ void step_nn(const SlotDesc *__restrict__ slots, int 
     const int x1 = min(x0 + 64 * W, (nx + 63) & ~63);
     const int xw = x0 + 64 * wave;
     const bool active = xw < nx;
+    // the one wavefront that completes inlet nodes (column 0, and the halo
+    // nodes beyond it that it gathers)
+    const bool inlet_wave = xw == 0;
     const int y0 = tyi * S.strip;
     const int y1 = min(y0 + S.strip, ny);
     const bool yper = S.flags & F_YPER;
@@ -350,10 +353,10 @@ __device__ __forceinline__ void step_nn(const SlotDesc *__restrict__ slots, int 
     Node cur;
     {
         const bool have_b = gathered(ys - d);
-        const RowSrc rwb = make_row<ST>(S, have_b ? real_row(ys - d) : ys);
+        const RowSrc rwb = make_row<ST>(S, have_b ? real_row(ys - d) : ys, inlet_wave);
         Pend rb;
         if (have_b) rb = issue_row(rwb);
-        const RowSrc rw0 = make_row<ST>(S, ys);
+        const RowSrc rw0 = make_row<ST>(S, ys, inlet_wave);
         const Pend r0 = issue_row(rw0);
         if (have_b) {
             const Own ob = finish_own(rb, rwb);
@@ -372,7 +375,7 @@ __device__ __forceinline__ void step_nn(const SlotDesc *__restrict__ slots, int 
         }
     }
     bool have_p = gathered(ys + d);
-    RowSrc rwp = make_row<ST>(S, have_p ? real_row(ys + d) : ys);
+    RowSrc rwp = make_row<ST>(S, have_p ? real_row(ys + d) : ys, inlet_wave);
     Pend pend;
     if (have_p) pend = issue_row(rwp);
 
@@ -392,7 +395,7 @@ __device__ __forceinline__ void step_nn(const SlotDesc *__restrict__ slots, int 
         const bool had_p = have_p;
         have_p = (d > 0 ? r2 <= y1 : r2 >= y0 - 1) && gathered(r2);
         if (have_p) {
-            rwp = make_row<ST>(S, real_row(r2));
+            rwp = make_row<ST>(S, real_row(r2), inlet_wave);
             pend = issue_row(rwp);
         }
         if (had_p) {
@@ -453,6 +456,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
     constexpr int kHalo = wave_halo(ISO, false), kOut = wave_cols(ISO, false);
     const int xw = (txi * W + (int)(threadIdx.x >> 6)) * kOut;
     if (xw >= nx) return;                      // uniform per wavefront
+    const bool inlet_wave = xw == 0;           // its lanes hold column 0 (and the clamped columns before it)
     const int y0 = tyi * S.strip;
     const int y1 = min(y0 + S.strip, ny);
     const bool yper = S.flags & F_YPER;
@@ -566,10 +570,10 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         {
             const bool hb2 = gathered(ys - 2 * d), hb1 = gathered(ys - d), ha1 = gathered(ys + d);
             Raw18<ST> rb2, rb1, ra1;
-            const RowSrc wb2 = make_row<ST>(S, hb2 ? real_row(ys - 2 * d) : ys);
-            const RowSrc wb1 = make_row<ST>(S, hb1 ? real_row(ys - d) : ys);
-            const RowSrc w0 = make_row<ST>(S, ys);
-            const RowSrc wa1 = make_row<ST>(S, ha1 ? real_row(ys + d) : ys);
+            const RowSrc wb2 = make_row<ST>(S, hb2 ? real_row(ys - 2 * d) : ys, inlet_wave);
+            const RowSrc wb1 = make_row<ST>(S, hb1 ? real_row(ys - d) : ys, inlet_wave);
+            const RowSrc w0 = make_row<ST>(S, ys, inlet_wave);
+            const RowSrc wa1 = make_row<ST>(S, ha1 ? real_row(ys + d) : ys, inlet_wave);
             if (hb2) rb2 = issue<ST>(S, src, xc, wb2);
             if (hb1) rb1 = issue<ST>(S, src, xc, wb1);
             const Raw18<ST> r0 = issue<ST>(S, src, xc, w0);
@@ -602,7 +606,8 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         }
         bool hp = wanted(ys + 2 * d);
         Raw18<ST> pend;
-        if (hp) pend = issue<ST>(S, src, xc, make_row<ST>(S, real_row(ys + 2 * d)));
+        RowSrc wp = make_row<ST>(S, hp ? real_row(ys + 2 * d) : ys, inlet_wave);
+        if (hp) pend = issue<ST>(S, src, xc, wp);
 
         const float fd = (float)d;
         for (int y = ys; y != ye; y += d) {
@@ -610,7 +615,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
             float ca2;
             QRow q2{};
             if (hp) {
-                nn = finish<ST>(S, pend, xc, make_row<ST>(S, real_row(y + 2 * d)));
+                nn = finish<ST>(S, pend, xc, wp);
                 ca2 = color_field(S, nn.rr(), nn.rb());
                 if (nsc) q2 = qreal(nn);
             } else if (gathered(y + d)) {       // row y+2d is the ghost row next to a wall
@@ -620,7 +625,10 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
                 ca2 = ca1;
             }
             hp = wanted(y + 3 * d);
-            if (hp) pend = issue<ST>(S, src, xc, make_row<ST>(S, real_row(y + 3 * d)));
+            if (hp) {
+                wp = make_row<ST>(S, real_row(y + 3 * d), inlet_wave);
+                pend = issue<ST>(S, src, xc, wp);
+            }
             const Psi5 pb2 = psi5(cb2), pb1 = psi5(cb1), p0 = psi5(c0), pa1 = psi5(ca1), pa2 = psi5(ca2);
             if (out_lane) {
                 // F_x = sum over rows dy of w(1+dy^2) (psi(+1) - psi(-1)) + 2 w(4+dy^2) (psi(+2) - psi(-2));
@@ -663,9 +671,9 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
     {
         const bool have_b = gathered(ys - d);
         Raw18<ST> rb;
-        const RowSrc rwb = make_row<ST>(S, have_b ? real_row(ys - d) : ys);
+        const RowSrc rwb = make_row<ST>(S, have_b ? real_row(ys - d) : ys, inlet_wave);
         if (have_b) rb = issue<ST>(S, src, xc, rwb);
-        const RowSrc rw0 = make_row<ST>(S, ys);
+        const RowSrc rw0 = make_row<ST>(S, ys, inlet_wave);
         const Raw18<ST> r0 = issue<ST>(S, src, xc, rw0);
         if (have_b) {
             const Node t = finish<ST>(S, rb, xc, rwb);
@@ -681,7 +689,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         }
     }
     bool have_p = gathered(ys + d);
-    RowSrc rwp = make_row<ST>(S, have_p ? real_row(ys + d) : ys);
+    RowSrc rwp = make_row<ST>(S, have_p ? real_row(ys + d) : ys, inlet_wave);
     Raw18<ST> pend;
     if (have_p) pend = issue<ST>(S, src, xc, rwp);
 
@@ -702,7 +710,7 @@ __device__ __forceinline__ void step_body(const SlotDesc *__restrict__ slots, in
         const int r2 = y + 2 * d;
         have_p = (d > 0 ? r2 <= y1 : r2 >= y0 - 1) && gathered(r2);
         if (have_p) {
-            rwp = make_row<ST>(S, real_row(r2));
+            rwp = make_row<ST>(S, real_row(r2), inlet_wave);
             pend = issue<ST>(S, src, xc, rwp);
         }
         if (out_lane) {
@@ -803,7 +811,7 @@ __global__ void __launch_bounds__(256) k_moments(const SlotDesc *__restrict__ sd
          c += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(c / S.nx), x = (int)(c - (long long)y * S.nx);
         const XCols xc = make_cols<ST>(S, x);
-        const RowSrc rw = make_row<ST>(S, y);
+        const RowSrc rw = make_row<ST>(S, y, xc.inlet);
         const Node nd = finish<ST>(S, issue<ST>(S, src, xc, rw), xc, rw);
         const float rho = nd.rr() + nd.rb();
         float ux, uy;
