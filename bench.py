@@ -365,7 +365,7 @@ def run_serve(args, log):
         x, y = dp_of(da, r), dp_of(b, r)
         if x is not None and y is not None:
             dpdiff.append(abs(x[0] - y[0]) / y[1])
-            if abs(y[0] / y[1] - 1.0) < 0.1:      # bubble has settled: FP32 within 10% of Laplace
+            if abs(y[0] / y[1] - 1.0) < 0.1:      # FP32's jump within 10% of Laplace at the request's step
                 dpsettled.append(abs(x[0] - y[0]) / y[1])
     if args.records:
         with open(args.records, "w") as fh:
@@ -404,9 +404,14 @@ def run_serve(args, log):
             laplace_dp_vs_fp32=dict(n=len(dpdiff), max=max(dpdiff) if dpdiff else None,
                                     p99=pct(dpdiff, 99), median=pct(dpdiff, 50),
                                     over_1pct=int(sum(d > 0.01 for d in dpdiff)),
-                                    settled_n=len(dpsettled), settled_max=max(dpsettled) if dpsettled else None,
-                                    settled_median=pct(dpsettled, 50),
-                                    settled_over_1pct=int(sum(d > 0.01 for d in dpsettled))),
+                                    near_laplace_n=len(dpsettled),
+                                    near_laplace_max=max(dpsettled) if dpsettled else None,
+                                    near_laplace_median=pct(dpsettled, 50),
+                                    near_laplace_over_1pct=int(sum(d > 0.01 for d in dpsettled)),
+                                    note="near_laplace: FP32's jump within 10% of sigma/R at the request's step "
+                                         "count, which a bubble can pass mid-oscillation; --workload "
+                                         "serve-laplace tells settled bubbles by running FP32 four times "
+                                         "longer"),
             mass_drift=dict(served_max=max(mdrift16) if mdrift16 else None,
                             fp32_max=max(mdrift32) if mdrift32 else None),
         ),
